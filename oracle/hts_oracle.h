@@ -1,0 +1,91 @@
+/*
+ * hts_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow FP64 CPU reference of one iteration of hyperbolic t-SNE in the
+ * Poincare disk, written from "Accelerating hyperbolic t-SNE" (arXiv
+ * 2401.13708).  Only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.  It shares no code, header, table or helper with
+ * the HIP library; both are written independently from the paper.
+ *
+ * All arrays are host arrays.  Points Y are n x 2 row-major doubles inside the
+ * unit disk; CSR affinities are (row_ptr int64[n+1], col int32[nnz], val
+ * double[nnz]) with columns ascending in each row and sum(val) = 1.
+ *
+ * Return codes: 0 ok, -1 invalid argument, -2 out of memory, -4 capacity.
+ */
+#ifndef HTS_ORACLE_H
+#define HTS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- geometry (Sec. 2-C, Sec. 4-B) ---- */
+double ora_dist(double ax, double ay, double bx, double by);           /* eq. (8) */
+void ora_dist_grad(double ax, double ay, double bx, double by, double *g); /* eq. (13): d d(a,b)/d a */
+void ora_mobius_add(double ax, double ay, double bx, double by, double *out); /* eq. (17) */
+void ora_exp_map(double yx, double yy, double vx, double vy, double *out);    /* eq. (16) */
+void ora_einstein_midpoint(const double *Y, int64_t n, double *out);          /* eq. (11) */
+
+/* ---- input affinities (Sec. 2-A, eq. (1); truncated Gaussians) ---- */
+int ora_knn_rows(const double *X, int64_t n, int32_t d, int32_t k,
+                 const int64_t *rows, int64_t nrows,
+                 int32_t *idx_out, double *d2_out);
+int ora_cond_p(const double *d2, int64_t n, int32_t k, double perplexity,
+               double *p_out, double *beta_out);
+int ora_symmetrize(const int32_t *knn, const double *pc, int64_t n, int32_t k,
+                   int64_t *row_ptr, int32_t *col, double *val, int64_t cap_nnz,
+                   int64_t *nnz_out);
+int ora_build_affinities(const double *X, int64_t n, int32_t d, double perplexity,
+                         int32_t k, int32_t *knn_out, int64_t *row_ptr,
+                         int32_t *col, double *val, int64_t cap_nnz,
+                         int64_t *nnz_out);
+
+/* ---- cost and exact gradient (eqs. (3), (12)-(15)) ---- */
+int ora_kl_cost(const double *Y, int64_t n, const int64_t *row_ptr,
+                const int32_t *col, const double *val, double exaggeration,
+                double *cost_out);
+int ora_gradient_exact(const double *Y, int64_t n, const int64_t *row_ptr,
+                       const int32_t *col, const double *val,
+                       double exaggeration, double *grad, double *z_out);
+/* exact gradient rows for a subset of queries; z is given (sum over all pairs) */
+int ora_gradient_exact_rows(const double *Y, int64_t n, const int64_t *row_ptr,
+                            const int32_t *col, const double *val,
+                            double exaggeration, const int64_t *rows,
+                            int64_t nrows, double z, double *grad_rows);
+int ora_z_exact(const double *Y, int64_t n, double *z_out);
+
+/* ---- polar quadtree (Sec. 2-D, Sec. 4-A) ---- */
+typedef struct ora_tree ora_tree;
+int ora_tree_build(const double *Y, int64_t n, int32_t max_depth,
+                   ora_tree **out);                       /* by insertion */
+int ora_tree_build_partition(const double *Y, int64_t n, int32_t max_depth,
+                             ora_tree **out);             /* by recursive split */
+void ora_tree_free(ora_tree *t);
+int64_t ora_tree_num_nodes(const ora_tree *t);
+/* pre-order export; any pointer may be NULL.  mid is n_nodes x 2, bounds is
+ * n_nodes x 4 (r_lo, r_hi, phi_lo, phi_hi), perm is the leaf-order point list */
+int ora_tree_export(const ora_tree *t, int32_t *count, int32_t *depth,
+                    int32_t *first, int32_t *next, double *mid, double *r_cell,
+                    double *bounds, int64_t *perm);
+
+/* ---- Barnes-Hut gradient (eq. (19) and the traversal of Sec. 4-B) ---- */
+int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
+                    const int32_t *col, const double *val, double exaggeration,
+                    const ora_tree *t, double theta, double *grad,
+                    double *z_out, int64_t *counters /* tests, accepts, leaf pairs; or NULL */);
+
+/* ---- Riemannian step (eqs. (7), (16)-(18), Sec. 5 optimiser) ---- */
+int ora_step(double *Y, double *update, double *gains, const double *grad,
+             int64_t n, double eta, double momentum, double min_gain,
+             double boundary_eps, int32_t metric_power);
+
+/* threads used by the parallel loops (0 = OpenMP default) */
+void ora_set_threads(int32_t nthreads);
+int32_t ora_get_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

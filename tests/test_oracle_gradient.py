@@ -1,0 +1,154 @@
+"""Pins of the oracle's cost, exact gradient and Barnes-Hut gradient
+(eqs. (3), (12)-(15), (19)) against finite differences, brute force, symmetry,
+the Euclidean limit (eq. (4)) and the theta = 0 reduction (Sec. 5)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_13708_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _problem(n=48, seed=0, stage="mid", perplexity=5.0, k=15):
+    X = synth.gaussian_mixture(n, 8, n_clusters=4, seed=seed)
+    _, rp, col, val = oracle.build_affinities(X, perplexity, k)
+    Y = synth.disk_state(n, stage, n_clusters=4, seed=seed + 100).astype(np.float64)
+    return Y, rp, col, val
+
+
+@pytest.mark.parametrize("stage,ex", [("mid", 1.0), ("early", 1.0), ("late", 1.0), ("mid", 12.0)])
+def test_exact_gradient_is_the_cost_derivative(stage, ex):
+    Y, rp, col, val = _problem(40, seed=1, stage=stage)
+    g, _ = oracle.gradient_exact(Y, rp, col, val, ex)
+    # central differences of the cost, step scaled to the local metric
+    fd = np.zeros_like(Y)
+    for i in range(Y.shape[0]):
+        h = 1e-6 * (1 - Y[i] @ Y[i])
+        for c in range(2):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[i, c] += h
+            Ym[i, c] -= h
+            fd[i, c] = (oracle.kl_cost(Yp, rp, col, val, ex) - oracle.kl_cost(Ym, rp, col, val, ex)) / (2 * h)
+    err = np.linalg.norm(g - fd) / np.linalg.norm(g)
+    assert err < 1e-6, err
+
+
+def test_printed_gradient_without_distance_factor_fails_fd():
+    # eq. (14) as printed omits the factor d_ij; that form is not the derivative
+    Y, rp, col, val = _problem(24, seed=2)
+    g, z = oracle.gradient_exact(Y, rp, col, val, 1.0)
+    n = Y.shape[0]
+    lit = np.zeros_like(Y)
+    P = np.zeros((n, n))
+    for i in range(n):
+        P[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                continue
+            d = oracle.dist(Y[i], Y[j])
+            w = 1 / (1 + d * d)
+            lit[i] += 4 * (P[i, j] - w / z) * w * oracle.dist_grad(Y[i], Y[j])
+    assert np.linalg.norm(lit - g) / np.linalg.norm(g) > 0.05
+
+
+def test_z_brute_force():
+    Y, rp, col, val = _problem(30, seed=3)
+    _, z = oracle.gradient_exact(Y, rp, col, val)
+    # independent evaluation: arccosh of the eq. (8) argument, ordered pairs
+    n = Y.shape[0]
+    s = 0.0
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                a, b = Y[i], Y[j]
+                gam = 1 + 2 * (a - b) @ (a - b) / ((1 - a @ a) * (1 - b @ b))
+                s += 1 / (1 + np.arccosh(gam) ** 2)
+    assert z == pytest.approx(s, rel=1e-12)
+    assert oracle.z_exact(Y) == pytest.approx(s, rel=1e-12)
+
+
+def test_rotation_covariance():
+    Y, rp, col, val = _problem(36, seed=4)
+    th = 1.234
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    g0, z0 = oracle.gradient_exact(Y, rp, col, val, 4.0)
+    g1, z1 = oracle.gradient_exact(Y @ R.T, rp, col, val, 4.0)
+    assert np.allclose(g1, g0 @ R.T, rtol=1e-10, atol=1e-12 * np.abs(g0).max())
+    assert z1 == pytest.approx(z0, rel=1e-12)
+
+
+def _euclid_grad(Y, P):
+    # textbook Euclidean t-SNE gradient, eq. (4)
+    D = Y[:, None, :] - Y[None, :, :]
+    W = 1 / (1 + np.sum(D * D, -1))
+    np.fill_diagonal(W, 0)
+    Q = W / W.sum()
+    return 4 * np.sum(((P - Q) * W)[:, :, None] * D, axis=1)
+
+
+@pytest.mark.parametrize("scale,tol", [(1e-2, 3e-3), (1e-4, 1e-6)])
+def test_near_origin_limit_is_euclidean_tsne(scale, tol):
+    # near the origin d^H ~ 2 |y_i - y_j|, so g_H(Y) ~ 2 g_E(2 Y) with the error O(|y|^2)
+    n = 40
+    X = synth.gaussian_mixture(n, 6, n_clusters=4, seed=5)
+    _, rp, col, val = oracle.build_affinities(X, 5.0, 15)
+    P = np.zeros((n, n))
+    for i in range(n):
+        P[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    Y = synth.rng(6).normal(size=(n, 2)) * scale
+    gh, _ = oracle.gradient_exact(Y, rp, col, val)
+    ge = 2 * _euclid_grad(2 * Y, P)
+    assert np.linalg.norm(gh - ge) / np.linalg.norm(ge) < tol
+
+
+@pytest.mark.parametrize("stage", ["init", "early", "mid", "late", "edge"])
+def test_bh_theta_zero_equals_exact(stage):
+    Y, rp, col, val = _problem(60, seed=7, stage=stage)
+    t = oracle.Tree(Y)
+    gb, zb, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.0, 12.0)
+    ge, ze = oracle.gradient_exact(Y, rp, col, val, 12.0)
+    assert cnt["accepts"] == 0
+    assert cnt["pairs"] == 60 * 59
+    assert zb == pytest.approx(ze, rel=1e-12)
+    assert np.allclose(gb, ge, rtol=1e-10, atol=1e-12 * np.abs(ge).max())
+
+
+def test_bh_theta_zero_with_duplicates():
+    Y, rp, col, val = _problem(50, seed=8)
+    Y[10] = Y[11] = Y[12]
+    Y[20] = Y[3]
+    t = oracle.Tree(Y)
+    gb, zb, _ = oracle.gradient_bh(Y, rp, col, val, t, 0.0)
+    ge, ze = oracle.gradient_exact(Y, rp, col, val)
+    assert zb == pytest.approx(ze, rel=1e-12)
+    assert np.allclose(gb, ge, rtol=1e-10, atol=1e-12 * np.abs(ge).max())
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_bh_error_band_and_growth():
+    # the gradient error of Table 3 (theta = 0.5) is about 1e-3 to 2.7e-3; on
+    # synthetic data of the same kind the error must be of that order, and
+    # it must grow with theta (Sec. 5, effect of theta)
+    with open(os.path.join(GOLDEN, "paper_table3_gradient_error.json")) as f:
+        band = json.load(f)
+    lo, hi = min(band["gradient_error_theta_0_5"].values()), max(band["gradient_error_theta_0_5"].values())
+    n = 1500
+    X = synth.gaussian_mixture(n, 16, seed=9)
+    _, rp, col, val = oracle.build_affinities(X, 30.0, 90)
+    Y = synth.disk_state(n, "mid", seed=10).astype(np.float64)
+    ge, ze = oracle.gradient_exact(Y, rp, col, val)
+    t = oracle.Tree(Y)
+    errs = {}
+    for th in (0.3, 0.5, 0.8):
+        gb, zb, _ = oracle.gradient_bh(Y, rp, col, val, t, th)
+        errs[th] = _rel(gb, ge)
+    assert errs[0.3] < errs[0.5] < errs[0.8]
+    assert lo / 30 < errs[0.5] < hi * 10, (errs, lo, hi)
