@@ -103,17 +103,18 @@ void ora_exp_map(double yx, double yy, double vx, double vy, double *out) {
 /* Einstein midpoint, eq. (11) (Sec. 4-A): the points are mapped to the Klein
  * model, v = 2 y / (1 + |y|^2), averaged with weights gamma(v) =
  * 1 / sqrt(1 - |v|^2), and the average is mapped back to the Poincare disk,
- * y = v / (1 + sqrt(1 - |v|^2)). */
+ * y = v / (1 + sqrt(1 - |v|^2)).  For this v, gamma(v) v = lambda_y y and
+ * gamma(v) = (1 + |y|^2) / (1 - |y|^2) exactly; the sums use these forms
+ * because 1 - |v|^2 cancels to a few digits near the rim. */
 void ora_einstein_midpoint(const double *Y, int64_t n, double *out) {
     double sx = 0.0, sy = 0.0, sg = 0.0;
     for (int64_t j = 0; j < n; ++j) {
         double x = Y[2 * j], y = Y[2 * j + 1];
         double r2 = x * x + y * y;
-        double vx = 2.0 * x / (1.0 + r2), vy = 2.0 * y / (1.0 + r2);
-        double g = 1.0 / sqrt(1.0 - (vx * vx + vy * vy));
-        sx += g * vx;
-        sy += g * vy;
-        sg += g;
+        double a = 1.0 - r2;
+        sx += 2.0 * x / a;
+        sy += 2.0 * y / a;
+        sg += (1.0 + r2) / a;
     }
     double kx = sx / sg, ky = sy / sg;
     double den = 1.0 + sqrt(1.0 - (kx * kx + ky * ky));
@@ -881,7 +882,10 @@ int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
  *   y      <- exp_y(u), eq. (16); reading: the momentum vector is reused at
  *           the new point without transport;
  *   proj   eq. (18); reading: "y/|y| - eps" is read as (1 - eps) y / |y|,
- *           applied when |y| >= 1. */
+ *           applied when |y| >= 1, tested as |y|^2 >= 1 - 2^-50: a point
+ *           on the circle up to the rounding of its double-precision norm
+ *           counts as on it (else 1 - |y|^2 could round to 0 next). */
+#define ON_CIRCLE (1.0 - 0x1p-50)
 int ora_step(double *Y, double *update, double *gains, const double *grad,
              int64_t n, double eta, double momentum, double min_gain,
              double boundary_eps, int32_t metric_power) {
@@ -901,8 +905,9 @@ int ora_step(double *Y, double *update, double *gains, const double *grad,
         }
         double out[2];
         ora_exp_map(x, y, update[2 * i], update[2 * i + 1], out);
-        double nr = sqrt(out[0] * out[0] + out[1] * out[1]);
-        if (nr >= 1.0) {
+        double r2 = out[0] * out[0] + out[1] * out[1];
+        if (r2 >= ON_CIRCLE) {
+            double nr = sqrt(r2);
             out[0] = (1.0 - boundary_eps) * out[0] / nr;
             out[1] = (1.0 - boundary_eps) * out[1] / nr;
         }

@@ -172,4 +172,6 @@ def test_midpoints_are_einstein_midpoints_of_cells():
         gm = 1 / np.sqrt(1 - np.sum(v * v, 1))
         K = (gm[:, None] * v).sum(0) / gm.sum()
         m = K / (1 + np.sqrt(1 - K @ K))
-        assert np.allclose(e["mid"][k], m, rtol=1e-11, atol=1e-15)
+        # the printed form divides by sqrt(1 - |v|^2), which cancels near the rim
+        tol = 1e-12 + 1e-16 / np.min(1 - np.sum(pts * pts, 1)) ** 2
+        assert np.allclose(e["mid"][k], m, rtol=tol, atol=1e-15)
