@@ -1,0 +1,198 @@
+/*
+ * hts.h -- C ABI of the MI355X (gfx950) hyperbolic t-SNE gradient library.
+ *
+ * Computes one iteration of hyperbolic t-SNE in the Poincare disk as defined
+ * in "Accelerating hyperbolic t-SNE" (arXiv 2401.13708): the sparse
+ * attractive sum over the affinities P, the repulsive sum with its
+ * normaliser Z (exactly, or by Barnes-Hut over a polar quadtree), and the
+ * Riemannian gradient step.
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer owned by the caller, contiguous
+ *    and naturally aligned, unless marked "host".  The library never frees or
+ *    keeps a caller pointer beyond the call.
+ *  - Points are n x 2 row-major (x, y) pairs strictly inside the unit disk.
+ *    dtype HTS_F32: float arrays; HTS_F64: double arrays.  Y, P values,
+ *    gradients, update and gains of one call share the dtype.
+ *  - Affinities P are CSR: row_ptr int64[n+1], col_idx int32[nnz] (columns
+ *    ascending in each row, no diagonal), p_val[nnz] with sum 1.
+ *  - stream is a hipStream_t (NULL: the null stream).  Calls are asynchronous
+ *    on it except those marked "sync", which return after the stream has
+ *    drained.  Calls on one context must not overlap on different streams.
+ *  - Arguments are validated before anything is launched; a failed check
+ *    returns HTS_EINVAL and launches nothing.  hts_last_error() gives the
+ *    message of the last failure on the calling thread.
+ *  - Numerical faults found on the device (NaN or infinite gradients,
+ *    points outside the disk) set a device error word that the next sync
+ *    call or hts_check() reports as HTS_ENUMERIC.
+ */
+#ifndef HTS_H
+#define HTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hts_status {
+    HTS_OK = 0,
+    HTS_EINVAL = -1,     /* invalid argument (nothing launched) */
+    HTS_ENOMEM = -2,     /* device allocation failed */
+    HTS_EDEVICE = -3,    /* HIP runtime error */
+    HTS_ECAPACITY = -4,  /* an output capacity is too small; the size needed is returned */
+    HTS_ENUMERIC = -5    /* the device error word is set */
+} hts_status;
+
+typedef enum hts_dtype { HTS_F32 = 0, HTS_F64 = 1 } hts_dtype;
+
+/* device error word bits */
+#define HTS_ERR_NONFINITE_GRAD 1u
+#define HTS_ERR_OUTSIDE_DISK 2u
+#define HTS_ERR_NONFINITE_Y 4u
+#define HTS_ERR_BAD_INDEX 8u      /* a CSR column outside [0, n) was skipped */
+#define HTS_ERR_TREE_OVERFLOW 16u /* node storage exhausted (internal error) */
+
+typedef struct hts_ctx_s *hts_ctx;
+typedef struct hts_tree_s *hts_tree;
+typedef void *hts_stream;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *hts_last_error(void);
+
+/* Library version string. */
+const char *hts_version(void);
+
+/* Context on one device: owns the device error word and grow-on-demand
+ * workspaces.  device: HIP device ordinal.  *out receives the handle. */
+hts_status hts_create(int32_t device, hts_ctx *out);
+hts_status hts_destroy(hts_ctx ctx);
+
+/* sync: waits for the stream, returns HTS_ENUMERIC if the device error word
+ * is set (and clears it), otherwise HTS_OK.  *bits_out (host, may be NULL)
+ * receives the word. */
+hts_status hts_check(hts_ctx ctx, hts_stream stream, uint32_t *bits_out);
+
+/* ------------------------------------------------------------------------
+ * Input affinities P -- Sec. 2-A, eq. (1), truncated to the k nearest
+ * neighbours (Sec. 2-A, Sec. 4-B) and symmetrised.  sync.
+ *  X          n x d row-major input points, dtype x_dtype.
+ *  perplexity target perplexity of every conditional row, 0 < perplexity < k.
+ *  k          neighbours per point, 1 <= k < n, k <= 128.
+ *  knn_idx    n x k int32 output (nearest first; ties by smaller index) or NULL.
+ *  row_ptr, col_idx, p_val   CSR output of P = (P_c + P_c^T) / (2 n), p_val
+ *             in p_dtype; cap_nnz entries available (2 n k always suffice).
+ *  nnz_out    host: number of entries written, or needed on HTS_ECAPACITY.
+ * The k-NN search is exact: squared distances are summed in double precision
+ * over the dimensions in ascending order with fused multiply-adds.  The
+ * bandwidth of row i solves perplexity(P_i) = perplexity by 100 bisection
+ * steps in double precision.
+ * ---------------------------------------------------------------------- */
+hts_status hts_build_affinities(hts_ctx ctx, hts_stream stream, const void *X,
+                                int64_t n, int32_t d, int32_t x_dtype,
+                                double perplexity, int32_t k, int32_t *knn_idx,
+                                int64_t *row_ptr, int32_t *col_idx, void *p_val,
+                                int32_t p_dtype, int64_t cap_nnz,
+                                int64_t *nnz_out);
+
+/* ------------------------------------------------------------------------
+ * Polar quadtree -- Sec. 2-D and Sec. 4-A.  The root is the annulus
+ * [min r, max r] x [0, 2 pi) of the current points; every cell splits at the
+ * angular middle and at the radial middle in embedding radius (eq. (10)); a
+ * leaf holds one point, or all points that reach max_depth; internal nodes
+ * carry the Einstein midpoint of their points (eq. (11)) and their hyperbolic
+ * diameter.  Nodes are kept in depth-first pre-order, children in the order
+ * 2 * [outer half] + [upper angular half].
+ * ---------------------------------------------------------------------- */
+
+/* Tree storage for up to n_max points; max_depth in [1, 24] (20 is the
+ * default of the tree readings).  Allocates device memory once. */
+hts_status hts_tree_create(hts_ctx ctx, int64_t n_max, int32_t max_depth,
+                           hts_tree *out);
+hts_status hts_tree_destroy(hts_tree tree);
+
+/* Builds the tree of Y (n points, 2 <= n <= n_max) on the stream.  The tree
+ * keeps its own copy of everything it needs; Y may change afterwards. */
+hts_status hts_build_polar_tree(hts_ctx ctx, hts_stream stream, const void *Y,
+                                int64_t n, int32_t y_dtype, hts_tree tree);
+
+/* sync.  Copies the last built tree out in pre-order.  *n_nodes_out (host)
+ * receives the node count M; every non-NULL device array must hold cap
+ * entries (M <= cap, else HTS_ECAPACITY): count[M] points per node,
+ * depth[M], first[M] (position of the node's first point in perm), next[M]
+ * (pre-order index after the node's subtree), mid[2M] (midpoint, double),
+ * r_cell[M] (hyperbolic diameter, double), perm[n] (int32 point indices in
+ * leaf order). */
+hts_status hts_tree_export(hts_ctx ctx, hts_stream stream, hts_tree tree,
+                           int64_t *n_nodes_out, int64_t cap, int32_t *count,
+                           int32_t *depth, int32_t *first, int32_t *next,
+                           double *mid, double *r_cell, int32_t *perm);
+
+/* ------------------------------------------------------------------------
+ * Gradients -- eqs. (12)-(15) of Sec. 4-B, with the factor d_ij that the
+ * derivative of ln(1 + d^2)^-1 carries:
+ *   g_i = 4 ( a sum_j p_ij w_ij d_ij dd_ij/dy_i - (1/Z) sum_{j!=i} w_ij^2 d_ij dd_ij/dy_i ),
+ *   w_ij = (1 + d_ij^2)^-1,  Z = sum over ordered pairs k != l of w_kl,
+ * with a = exaggeration > 0.  grad (n x 2) receives this Euclidean variation
+ * (no metric rescaling); *z_dev (device double) receives Z.
+ * Single precision: forces in float with float accumulation; the distance
+ * argument 2|yi-yj|^2 / ((1-|yi|^2)(1-|yj|^2)), the criterion and Z in double.
+ * ---------------------------------------------------------------------- */
+
+/* Exact O(n^2) repulsion. */
+hts_status hts_gradient_exact(hts_ctx ctx, hts_stream stream, const void *Y,
+                              int64_t n, int32_t dtype, const int64_t *row_ptr,
+                              const int32_t *col_idx, const void *p_val,
+                              double exaggeration, void *grad, double *z_dev);
+
+/* Barnes-Hut repulsion (eq. (19)): a cell whose diameter r_cell and midpoint
+ * m satisfy r_cell / d(y_i, m) < theta stands for its N_cell points;
+ * theta = 0 evaluates every pair.  tree must have been built from the same Y.
+ * stats_dev: NULL or device uint64[3] to which the call ADDS the number of
+ * node tests, accepted cells and exact leaf pairs. */
+hts_status hts_gradient_bh(hts_ctx ctx, hts_stream stream, const void *Y,
+                           int64_t n, int32_t dtype, const int64_t *row_ptr,
+                           const int32_t *col_idx, const void *p_val,
+                           double exaggeration, hts_tree tree, double theta,
+                           void *grad, double *z_dev, uint64_t *stats_dev);
+
+/* ------------------------------------------------------------------------
+ * Riemannian step -- eqs. (7), (16)-(18) and the optimiser of Sec. 5.  In
+ * place on Y, update and gains (n x 2 each):
+ *   g_hat = s(y) grad, s = (1-|y|^2)^2 / 4 (metric_power 2: inverse metric)
+ *           or (1-|y|^2) / 2 (metric_power 1);
+ *   gains += 0.2 where sign(g_hat) != sign(update), else *= 0.8, >= min_gain;
+ *   update = momentum * update - eta * gains * g_hat;
+ *   y = exp_y(update) (Mobius addition), then y = (1 - boundary_eps) y / |y|
+ *       if |y| >= 1 (eq. (18)).
+ * The exponential map and the projection run in double precision.
+ * ---------------------------------------------------------------------- */
+hts_status hts_step(hts_ctx ctx, hts_stream stream, void *Y, void *update,
+                    void *gains, const void *grad, int64_t n, int32_t dtype,
+                    double eta, double momentum, double min_gain,
+                    double boundary_eps, int32_t metric_power);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing with HIP events on the caller's stream (for benchmarks).
+ * While enabled, each launch of a timed kernel class is bracketed by events.
+ * hts_timing_read (sync) adds the elapsed milliseconds and launch counts of
+ * the classes into ms_out[HTS_KCLASS_COUNT] / launches_out[...] (host) and
+ * resets them.
+ * ---------------------------------------------------------------------- */
+enum {
+    HTS_K_TREE = 0,      /* whole tree build */
+    HTS_K_ATTRACT = 1,   /* attractive CSR kernel */
+    HTS_K_TRAVERSE = 2,  /* Barnes-Hut traversal kernel */
+    HTS_K_EXACT = 3,     /* exact repulsion kernel */
+    HTS_K_FINALIZE = 4,  /* Z reduction and combine */
+    HTS_K_STEP = 5,      /* Riemannian step */
+    HTS_K_KNN = 6,       /* exact k-NN */
+    HTS_KCLASS_COUNT = 7
+};
+hts_status hts_timing_enable(hts_ctx ctx, int32_t on);
+hts_status hts_timing_read(hts_ctx ctx, double *ms_out, int64_t *launches_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HTS_H */

@@ -1,0 +1,450 @@
+// hts_api.hip -- the C ABI declared in include/hts.h: argument validation,
+// handles, workspaces and kernel dispatch.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "hts_impl.hpp"
+
+namespace hts {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+hts_status fail(hts_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+hts_status hip_fail(hipError_t e, const char *what) {
+    set_error("HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+    return e == hipErrorOutOfMemory ? HTS_ENOMEM : HTS_EDEVICE;
+}
+
+hts_status ensure(Buffer &b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return HTS_OK;
+    if (b.p) {
+        HTS_HIP(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes < 256 ? 256 : bytes;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    b.bytes = want;
+    return HTS_OK;
+}
+
+TimedScope::TimedScope(hts_ctx c, hipStream_t s, int k) : ctx(c), st(s), cls(k) {
+    if (!ctx || !ctx->timing.on) return;
+    Timing &tm = ctx->timing;
+    if (tm.used + 2 > tm.pool.size()) {
+        for (int a = 0; a < 64; ++a) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            tm.pool.push_back(e);
+        }
+    }
+    b = tm.pool[tm.used++];
+    hipEventRecord(b, st);
+}
+
+TimedScope::~TimedScope() {
+    if (!b) return;
+    Timing &tm = ctx->timing;
+    hipEvent_t e = tm.pool[tm.used++];
+    hipEventRecord(e, st);
+    tm.recs.push_back({cls, b, e});
+}
+
+extern hts_status tree_sort_bytes(int64_t n_max, int L, size_t *bytes);
+
+static bool dtype_ok(int32_t d) { return d == HTS_F32 || d == HTS_F64; }
+
+}  // namespace hts
+
+using namespace hts;
+
+extern "C" {
+
+const char *hts_last_error(void) { return hts::g_err; }
+
+const char *hts_version(void) { return "hts 0.1 (gfx950)"; }
+
+hts_status hts_create(int32_t device, hts_ctx *out) {
+    if (!out) return fail(HTS_EINVAL, "hts_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HTS_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return fail(HTS_EINVAL, "hts_create: device %d not in [0, %d)", device, ndev);
+    HTS_HIP(hipSetDevice(device));
+    hts_ctx c = new hts_ctx_s();
+    c->device = device;
+    hipError_t e = hipMalloc(&c->d_err, 64);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipMalloc(error word)");
+    }
+    e = hipMemset(c->d_err, 0, 64);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        hipFree(c->d_err);
+        delete c;
+        return hip_fail(e, "hipMemset(error word)");
+    }
+    *out = c;
+    return HTS_OK;
+}
+
+hts_status hts_destroy(hts_ctx c) {
+    if (!c) return fail(HTS_EINVAL, "hts_destroy: ctx is NULL");
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    Buffer *bufs[] = {&c->pts, &c->fattr, &c->frep, &c->zpart, &c->part, &c->spare};
+    for (Buffer *b : bufs)
+        if (b->p) hipFree(b->p);
+    for (Buffer &b : c->aff)
+        if (b.p) hipFree(b.p);
+    for (hipEvent_t e : c->timing.pool) hipEventDestroy(e);
+    hipFree(c->d_err);
+    delete c;
+    return HTS_OK;
+}
+
+hts_status hts_check(hts_ctx c, hts_stream stream, uint32_t *bits_out) {
+    if (!c) return fail(HTS_EINVAL, "hts_check: ctx is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t bits = 0;
+    HTS_HIP(hipStreamSynchronize(st));
+    HTS_HIP(hipMemcpy(&bits, c->d_err, sizeof(bits), hipMemcpyDeviceToHost));
+    if (bits_out) *bits_out = bits;
+    if (bits) {
+        HTS_HIP(hipMemset(c->d_err, 0, sizeof(uint32_t)));
+        return fail(HTS_ENUMERIC, "device error word 0x%x (1: non-finite gradient, 2: point outside the disk, 4: non-finite point)", bits);
+    }
+    return HTS_OK;
+}
+
+// ---------------------------------------------------------------- affinities
+hts_status hts_build_affinities(hts_ctx c, hts_stream stream, const void *X, int64_t n, int32_t d,
+                                int32_t x_dtype, double perplexity, int32_t k, int32_t *knn_idx,
+                                int64_t *row_ptr, int32_t *col_idx, void *p_val, int32_t p_dtype,
+                                int64_t cap_nnz, int64_t *nnz_out) {
+    if (n < 2) return fail(HTS_EINVAL, "hts_build_affinities: n = %lld < 2", (long long)n);
+    if (n > 0x7fffffff) return fail(HTS_EINVAL, "hts_build_affinities: n too large");
+    if (d < 1) return fail(HTS_EINVAL, "hts_build_affinities: d = %d < 1", d);
+    if (k < 1 || k >= n) return fail(HTS_EINVAL, "hts_build_affinities: k = %d not in [1, n)", k);
+    if (k > 128) return fail(HTS_EINVAL, "hts_build_affinities: k = %d > 128", k);
+    if (!(perplexity > 0.0) || !(perplexity < (double)k))
+        return fail(HTS_EINVAL, "hts_build_affinities: perplexity %g not in (0, k)", perplexity);
+    if (!dtype_ok(x_dtype) || !dtype_ok(p_dtype))
+        return fail(HTS_EINVAL, "hts_build_affinities: bad dtype");
+    if (!X || !row_ptr || !col_idx || !p_val || !nnz_out)
+        return fail(HTS_EINVAL, "hts_build_affinities: NULL pointer argument");
+    if (cap_nnz < 0) return fail(HTS_EINVAL, "hts_build_affinities: cap_nnz < 0");
+    if (!c) return fail(HTS_EINVAL, "hts_build_affinities: ctx is NULL");
+    HTS_HIP(hipSetDevice(c->device));
+    return affinities(c, (hipStream_t)stream, X, n, d, x_dtype, perplexity, k, knn_idx, row_ptr,
+                      col_idx, p_val, p_dtype, cap_nnz, nnz_out);
+}
+
+// ---------------------------------------------------------------- tree
+hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree *out) {
+    if (!out) return fail(HTS_EINVAL, "hts_tree_create: out is NULL");
+    *out = nullptr;
+    if (n_max < 2) return fail(HTS_EINVAL, "hts_tree_create: n_max < 2");
+    if (max_depth < 1 || max_depth > 24)
+        return fail(HTS_EINVAL, "hts_tree_create: max_depth %d not in [1, 24]", max_depth);
+    int64_t cap = n_max * (int64_t)(max_depth + 1) + 1;
+    if (cap >= kMaxNodes)
+        return fail(HTS_EINVAL, "hts_tree_create: n_max * (max_depth + 1) must stay below 2^26");
+    if (!c) return fail(HTS_EINVAL, "hts_tree_create: ctx is NULL");
+    HTS_HIP(hipSetDevice(c->device));
+    hts_tree t = new hts_tree_s();
+    t->ctx = c;
+    t->n_max = n_max;
+    t->max_depth = max_depth;
+    t->cap_nodes = cap;
+    t->nb = cdiv(n_max, kBlock);
+    size_t nm = (size_t)n_max;
+    struct A { void **p; size_t bytes; } allocs[] = {
+        {(void **)&t->r, nm * 8},
+        {(void **)&t->phi, nm * 8},
+        {(void **)&t->mm, (size_t)t->nb * 16},
+        {(void **)&t->root, 16},
+        {(void **)&t->keys_in, nm * 8},
+        {(void **)&t->keys, nm * 8},
+        {(void **)&t->idx_in, nm * 4},
+        {(void **)&t->perm, nm * 4},
+        {(void **)&t->ncnt_part, (size_t)t->nb * 4},
+        {(void **)&t->q_part, (size_t)t->nb * sizeof(DD3)},
+        {(void **)&t->node_start, (nm + 1) * 4},
+        {(void **)&t->psum, (nm + 1) * sizeof(DD3)},
+        {(void **)&t->d_m, 64},
+        {(void **)&t->spts, nm * sizeof(PointRec<double>)},
+        {(void **)&t->nodes, (size_t)cap * sizeof(NodeRec<double>)},
+        {(void **)&t->r_cell, (size_t)cap * 8},
+        {(void **)&t->node_first, (size_t)cap * 4},
+        {(void **)&t->sinhalf, 32 * 8},
+    };
+    hts_status s = HTS_OK;
+    for (auto &a : allocs) {
+        hipError_t e = hipMalloc(a.p, a.bytes);
+        if (e != hipSuccess) {
+            s = hip_fail(e, "hipMalloc(tree)");
+            break;
+        }
+    }
+    if (s == HTS_OK) s = tree_sort_bytes(n_max, max_depth, &t->sort_tmp_bytes);
+    if (s == HTS_OK) {
+        hipError_t e = hipMalloc(&t->sort_tmp, t->sort_tmp_bytes ? t->sort_tmp_bytes : 256);
+        if (e != hipSuccess) s = hip_fail(e, "hipMalloc(sort)");
+    }
+    if (s == HTS_OK) {
+        // sine of half the angular width of a depth-l cell, capped at 1 for
+        // the two top levels (widths 2 pi and pi)
+        double sh[32];
+        for (int l = 0; l < 32; ++l) sh[l] = l <= 1 ? 1.0 : std::sin(M_PI / std::ldexp(1.0, l));
+        hipError_t e = hipMemcpy(t->sinhalf, sh, sizeof(sh), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(t->d_m, 0, 64);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) s = hip_fail(e, "tree init");
+    }
+    if (s != HTS_OK) {
+        hts_tree_destroy(t);
+        return s;
+    }
+    *out = t;
+    return HTS_OK;
+}
+
+hts_status hts_tree_destroy(hts_tree t) {
+    if (!t) return fail(HTS_EINVAL, "hts_tree_destroy: tree is NULL");
+    hipSetDevice(t->ctx->device);
+    hipDeviceSynchronize();
+    void *ptrs[] = {t->r, t->phi, t->mm, t->root, t->keys_in, t->keys, t->idx_in, t->perm,
+                    t->sort_tmp, t->ncnt_part, t->q_part, t->node_start, t->psum, t->d_m,
+                    t->spts, t->nodes, t->r_cell, t->node_first, t->sinhalf};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    delete t;
+    return HTS_OK;
+}
+
+hts_status hts_build_polar_tree(hts_ctx c, hts_stream stream, const void *Y, int64_t n,
+                                int32_t y_dtype, hts_tree t) {
+    if (!c || !t) return fail(HTS_EINVAL, "hts_build_polar_tree: NULL handle");
+    if (t->ctx != c) return fail(HTS_EINVAL, "hts_build_polar_tree: tree belongs to another context");
+    if (n < 2 || n > t->n_max)
+        return fail(HTS_EINVAL, "hts_build_polar_tree: n = %lld not in [2, n_max = %lld]",
+                    (long long)n, (long long)t->n_max);
+    if (!dtype_ok(y_dtype)) return fail(HTS_EINVAL, "hts_build_polar_tree: bad dtype");
+    if (!Y) return fail(HTS_EINVAL, "hts_build_polar_tree: Y is NULL");
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (y_dtype == HTS_F64) return tree_build<double>(c, st, (const double *)Y, n, t);
+    return tree_build<float>(c, st, (const float *)Y, n, t);
+}
+
+}  // extern "C"
+__global__ void k_export_nodes(const void *nodes, int dtype, const int32_t *d_m,
+                               const double *r_cell, const int32_t *node_first, int64_t cap,
+                               int32_t *count, int32_t *depth, int32_t *first, int32_t *next,
+                               double *mid, double *rc) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t M = *d_m;
+    if (k >= M || k >= cap) return;
+    int32_t cnt;
+    uint32_t nxd;
+    double mx, my;
+    if (dtype == HTS_F64) {
+        NodeRec<double> r = ((const NodeRec<double> *)nodes)[k];
+        cnt = r.count; nxd = r.next_depth; mx = r.mx; my = r.my;
+    } else {
+        NodeRec<float> r = ((const NodeRec<float> *)nodes)[k];
+        cnt = r.count; nxd = r.next_depth; mx = r.mx; my = r.my;
+    }
+    if (count) count[k] = cnt;
+    if (depth) depth[k] = (int32_t)(nxd >> kNextBits);
+    if (next) next[k] = (int32_t)(nxd & kNextMask);
+    if (first) first[k] = node_first[k];
+    if (mid) { mid[2 * k] = mx; mid[2 * k + 1] = my; }
+    if (rc) rc[k] = r_cell[k];
+}
+
+__global__ void k_export_perm(const uint32_t *perm, int64_t n, int32_t *out) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = (int32_t)perm[i];
+}
+
+extern "C" hts_status hts_tree_export(hts_ctx c, hts_stream stream, hts_tree t, int64_t *n_nodes_out,
+                           int64_t cap, int32_t *count, int32_t *depth, int32_t *first,
+                           int32_t *next, double *mid, double *r_cell, int32_t *perm) {
+    if (!c || !t || !n_nodes_out) return fail(HTS_EINVAL, "hts_tree_export: NULL argument");
+    if (t->n < 2) return fail(HTS_EINVAL, "hts_tree_export: the tree has not been built");
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    int32_t M = 0;
+    HTS_HIP(hipMemcpyAsync(&M, t->d_m, sizeof(M), hipMemcpyDeviceToHost, st));
+    HTS_HIP(hipStreamSynchronize(st));
+    *n_nodes_out = M;
+    bool any = count || depth || first || next || mid || r_cell;
+    if (any && M > cap) return fail(HTS_ECAPACITY, "hts_tree_export: %d nodes > cap %lld", M, (long long)cap);
+    if (any) {
+        hipLaunchKernelGGL(k_export_nodes, dim3(cdiv(M, kBlock)), dim3(kBlock), 0, st, t->nodes,
+                           t->dtype, t->d_m, t->r_cell, t->node_first, cap, count, depth, first,
+                           next, mid, r_cell);
+        HTS_HIP(hipGetLastError());
+    }
+    if (perm) {
+        hipLaunchKernelGGL(k_export_perm, dim3(cdiv(t->n, kBlock)), dim3(kBlock), 0, st, t->perm,
+                           t->n, perm);
+        HTS_HIP(hipGetLastError());
+    }
+    HTS_HIP(hipStreamSynchronize(st));
+    return HTS_OK;
+}
+
+// ---------------------------------------------------------------- gradients
+static hts_status grad_args(const char *fn, hts_ctx c, const void *Y, int64_t n, int32_t dtype,
+                            const int64_t *rp, const int32_t *col, const void *val, double ex,
+                            void *grad, double *z_dev) {
+    if (n < 2) return fail(HTS_EINVAL, "%s: n = %lld < 2", fn, (long long)n);
+    if (n > 0x7fffffff) return fail(HTS_EINVAL, "%s: n too large", fn);
+    if (!dtype_ok(dtype)) return fail(HTS_EINVAL, "%s: bad dtype %d", fn, dtype);
+    if (!(ex > 0.0) || !std::isfinite(ex)) return fail(HTS_EINVAL, "%s: exaggeration %g must be > 0", fn, ex);
+    if (!Y || !rp || !col || !val || !grad || !z_dev) return fail(HTS_EINVAL, "%s: NULL pointer argument", fn);
+    if (!c) return fail(HTS_EINVAL, "%s: ctx is NULL", fn);
+    return HTS_OK;
+}
+
+template <typename T>
+static hts_status exact_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, const int64_t *rp,
+                             const int32_t *col, const T *val, double ex, T *grad, double *z_dev) {
+    HTS_OKR(ensure(c->pts, (size_t)n * sizeof(PointRec<T>)));
+    HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
+    HTS_OKR(ensure(c->frep, (size_t)n * 2 * sizeof(double)));
+    HTS_OKR(ensure(c->zpart, (size_t)(cdiv(n, kBlock) + 8) * sizeof(double)));
+    PointRec<T> *pts = (PointRec<T> *)c->pts.p;
+    HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
+    HTS_OKR(launch_attract<T>(c, st, pts, rp, col, val, n, (T *)c->fattr.p));
+    int64_t nz = 0;
+    HTS_OKR(launch_exact<T>(c, st, pts, n, (double *)c->frep.p, (double *)c->zpart.p, &nz));
+    return launch_finalize<T, double>(c, st, (const T *)c->fattr.p, (const double *)c->frep.p,
+                                      (const double *)c->zpart.p, nz, n, ex, grad, z_dev);
+}
+
+extern "C" hts_status hts_gradient_exact(hts_ctx c, hts_stream stream, const void *Y, int64_t n,
+                              int32_t dtype, const int64_t *row_ptr, const int32_t *col_idx,
+                              const void *p_val, double exaggeration, void *grad, double *z_dev) {
+    HTS_OKR(grad_args("hts_gradient_exact", c, Y, n, dtype, row_ptr, col_idx, p_val, exaggeration,
+                      grad, z_dev));
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == HTS_F64)
+        return exact_impl<double>(c, st, (const double *)Y, n, row_ptr, col_idx,
+                                  (const double *)p_val, exaggeration, (double *)grad, z_dev);
+    return exact_impl<float>(c, st, (const float *)Y, n, row_ptr, col_idx, (const float *)p_val,
+                             exaggeration, (float *)grad, z_dev);
+}
+
+template <typename T>
+static hts_status bh_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, const int64_t *rp,
+                          const int32_t *col, const T *val, double ex, hts_tree t, double theta,
+                          T *grad, double *z_dev, uint64_t *stats) {
+    HTS_OKR(ensure(c->pts, (size_t)n * sizeof(PointRec<T>)));
+    HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
+    HTS_OKR(ensure(c->frep, (size_t)n * 2 * sizeof(T)));
+    HTS_OKR(ensure(c->zpart, (size_t)(cdiv(n, kBlock) * (kBlock / kWave) + 8) * sizeof(double)));
+    PointRec<T> *pts = (PointRec<T> *)c->pts.p;
+    HTS_OKR(tree_thresholds(c, st, t, sizeof(T) == 8 ? HTS_F64 : HTS_F32, theta));
+    HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
+    HTS_OKR(launch_attract<T>(c, st, pts, rp, col, val, n, (T *)c->fattr.p));
+    int64_t nz = 0;
+    HTS_OKR(launch_traverse<T>(c, st, t, n, (T *)c->frep.p, (double *)c->zpart.p, &nz, stats));
+    return launch_finalize<T, T>(c, st, (const T *)c->fattr.p, (const T *)c->frep.p,
+                                 (const double *)c->zpart.p, nz, n, ex, grad, z_dev);
+}
+
+extern "C" {
+hts_status hts_gradient_bh(hts_ctx c, hts_stream stream, const void *Y, int64_t n, int32_t dtype,
+                           const int64_t *row_ptr, const int32_t *col_idx, const void *p_val,
+                           double exaggeration, hts_tree t, double theta, void *grad,
+                           double *z_dev, uint64_t *stats_dev) {
+    HTS_OKR(grad_args("hts_gradient_bh", c, Y, n, dtype, row_ptr, col_idx, p_val, exaggeration,
+                      grad, z_dev));
+    if (!(theta >= 0.0) || !std::isfinite(theta))
+        return fail(HTS_EINVAL, "hts_gradient_bh: theta %g must be finite and >= 0", theta);
+    if (!t) return fail(HTS_EINVAL, "hts_gradient_bh: tree is NULL");
+    if (t->ctx != c) return fail(HTS_EINVAL, "hts_gradient_bh: tree belongs to another context");
+    if (t->n != n) return fail(HTS_EINVAL, "hts_gradient_bh: tree was built for n = %lld, not %lld",
+                               (long long)t->n, (long long)n);
+    if (t->dtype != dtype) return fail(HTS_EINVAL, "hts_gradient_bh: tree built with another dtype");
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == HTS_F64)
+        return bh_impl<double>(c, st, (const double *)Y, n, row_ptr, col_idx, (const double *)p_val,
+                               exaggeration, t, theta, (double *)grad, z_dev, stats_dev);
+    return bh_impl<float>(c, st, (const float *)Y, n, row_ptr, col_idx, (const float *)p_val,
+                          exaggeration, t, theta, (float *)grad, z_dev, stats_dev);
+}
+
+// ---------------------------------------------------------------- step
+hts_status hts_step(hts_ctx c, hts_stream stream, void *Y, void *update, void *gains,
+                    const void *grad, int64_t n, int32_t dtype, double eta, double momentum,
+                    double min_gain, double boundary_eps, int32_t metric_power) {
+    if (n < 1) return fail(HTS_EINVAL, "hts_step: n < 1");
+    if (!dtype_ok(dtype)) return fail(HTS_EINVAL, "hts_step: bad dtype");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(HTS_EINVAL, "hts_step: eta must be > 0");
+    if (!(momentum >= 0.0) || !(momentum < 1.0)) return fail(HTS_EINVAL, "hts_step: momentum not in [0, 1)");
+    if (!(min_gain >= 0.0)) return fail(HTS_EINVAL, "hts_step: min_gain < 0");
+    if (!(boundary_eps > 0.0) || !(boundary_eps < 1.0)) return fail(HTS_EINVAL, "hts_step: boundary_eps not in (0, 1)");
+    if (metric_power != 1 && metric_power != 2) return fail(HTS_EINVAL, "hts_step: metric_power must be 1 or 2");
+    if (!Y || !update || !gains || !grad) return fail(HTS_EINVAL, "hts_step: NULL pointer argument");
+    if (!c) return fail(HTS_EINVAL, "hts_step: ctx is NULL");
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == HTS_F64)
+        return launch_step<double>(c, st, (double *)Y, (double *)update, (double *)gains,
+                                   (const double *)grad, n, eta, momentum, min_gain, boundary_eps,
+                                   metric_power);
+    return launch_step<float>(c, st, (float *)Y, (float *)update, (float *)gains,
+                              (const float *)grad, n, eta, momentum, min_gain, boundary_eps,
+                              metric_power);
+}
+
+// ---------------------------------------------------------------- timing
+hts_status hts_timing_enable(hts_ctx c, int32_t on) {
+    if (!c) return fail(HTS_EINVAL, "hts_timing_enable: ctx is NULL");
+    c->timing.on = on != 0;
+    return HTS_OK;
+}
+
+hts_status hts_timing_read(hts_ctx c, double *ms_out, int64_t *launches_out) {
+    if (!c || !ms_out || !launches_out) return fail(HTS_EINVAL, "hts_timing_read: NULL argument");
+    Timing &tm = c->timing;
+    for (auto &r : tm.recs) {
+        HTS_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HTS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.cls >= 0 && r.cls < HTS_KCLASS_COUNT) {
+            ms_out[r.cls] += ms;
+            launches_out[r.cls] += 1;
+        }
+    }
+    tm.recs.clear();
+    tm.used = 0;
+    return HTS_OK;
+}
+
+}  // extern "C"

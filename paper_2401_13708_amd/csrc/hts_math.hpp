@@ -1,0 +1,107 @@
+// hts_math.hpp -- device arithmetic shared by the gradient kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hts_impl.hpp"
+
+namespace hts {
+
+// acosh(1 + t) = log1p(t + sqrt(t (t + 2))) with full relative accuracy for
+// small t (eq. (8) with the argument carried as t = gamma - 1, never gamma).
+__device__ __forceinline__ float acosh1p(float t, float &sh) {
+    sh = __builtin_sqrtf(t * (t + 2.0f));
+    return log1pf(t + sh);
+}
+__device__ __forceinline__ double acosh1p(double t, double &sh) {
+    sh = sqrt(t * (t + 2.0));
+    return log1p(t + sh);
+}
+
+// One pair (query q, other point or cell midpoint o):
+//   t   = 2 |q - o|^2 ia_q ib_o        (double: the eq. (8) argument minus 1)
+//   d   = acosh(1 + t),  sinh d = sqrt(t (t + 2))
+//   w   = (1 + d^2)^-1
+//   d dd/dq = (d / sinh d) 4 ia_q ib_o ((q - o) + |q - o|^2 ia_q q)   (eq. (13))
+// The caller multiplies `base` by the weight it needs: p w (attraction) or
+// N w^2 (repulsion).
+template <typename T>
+struct PairTerm {
+    T w;      // (1 + d^2)^-1
+    T base;   // (d / sinh d) 4 ia ib
+    T vx, vy; // (q - o) + |q - o|^2 ia_q q
+};
+
+// distance argument in double from coordinates in T
+template <typename T>
+__device__ __forceinline__ double dist_arg(T qx, T qy, double qia, T ox, T oy, double oib, double &dd) {
+    double dx = (double)qx - (double)ox;
+    double dy = (double)qy - (double)oy;
+    dd = dx * dx + dy * dy;
+    return 2.0 * dd * qia * oib;
+}
+
+template <typename T>
+__device__ __forceinline__ PairTerm<T> pair_term(T qx, T qy, double qia, T ox, T oy, double oib,
+                                                 double t, double dd) {
+    PairTerm<T> r;
+    T tf = (T)t;
+    T sh;
+    T d = acosh1p(tf, sh);
+    r.w = (T)1 / ((T)1 + d * d);
+    T ratio = sh > (T)0 ? d / sh : (T)1;
+    r.base = ratio * (T)(4.0 * qia * oib);
+    T c = (T)(dd * qia);
+    r.vx = (qx - ox) + c * qx;
+    r.vy = (qy - oy) + c * qy;
+    return r;
+}
+
+// ---------------------------------------------------------------- wave ops
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// double-double (Dekker/Knuth two-sum) for the prefix sums of the midpoint
+// summands: the difference of two prefix sums keeps the node's own digits.
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ DD3 dd_add(const DD3 &a, const DD3 &b) {
+    DD3 r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double s, e;
+        two_sum(a.hi[c], b.hi[c], s, e);
+        e += a.lo[c] + b.lo[c];
+        double h = s + e;
+        r.lo[c] = e - (h - s);
+        r.hi[c] = h;
+    }
+    return r;
+}
+__device__ __forceinline__ DD3 dd_zero() {
+    DD3 r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r.hi[c] = r.lo[c] = 0.0;
+    return r;
+}
+
+}  // namespace hts

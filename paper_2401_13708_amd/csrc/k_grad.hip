@@ -1,0 +1,323 @@
+// k_grad.hip -- gradient kernels: point records, attractive CSR sum, exact
+// repulsion, Z reduction + combine, and the Riemannian step.
+#include "hts_impl.hpp"
+#include "hts_math.hpp"
+
+namespace hts {
+
+// ---------------------------------------------------------------- points
+// PointRec with ia = 1 / (1 - |y|^2) in double (the conformal factor of
+// eq. (7) is lambda = 2 ia).  Flags points outside the open disk.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prep_points(const T *__restrict__ Y, int64_t n,
+                                                        PointRec<T> *__restrict__ pts,
+                                                        uint32_t *__restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    T x = Y[2 * i], y = Y[2 * i + 1];
+    double a = 1.0 - ((double)x * (double)x + (double)y * (double)y);
+    PointRec<T> p;
+    p.x = x;
+    p.y = y;
+    p.ia = 1.0 / a;
+    if constexpr (sizeof(T) == 8) p.pad = 0.0;
+    if (!(a > 0.0)) atomicOr(err, (a == a) ? HTS_ERR_OUTSIDE_DISK : HTS_ERR_NONFINITE_Y);
+    pts[i] = p;
+}
+
+template <typename T>
+hts_status launch_prep_points(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, PointRec<T> *pts) {
+    hipLaunchKernelGGL(k_prep_points<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, Y, n, pts,
+                       ctx->d_err);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
+// ---------------------------------------------------------------- attraction
+// First sum of eq. (15): F_attr,i = sum_{j in row i} p_ij w_ij d_ij dd_ij/dy_i.
+// G lanes share a CSR row; column/value reads are contiguous per row, the
+// point records of the columns are gathered (they stay in L2).
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_attract(const PointRec<T> *__restrict__ pts,
+                                                    const int64_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ col,
+                                                    const T *__restrict__ val, int64_t n,
+                                                    T *__restrict__ fattr,
+                                                    uint32_t *__restrict__ err) {
+    int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t row = gid / G;
+    int sub = (int)(gid % G);
+    T fx = 0, fy = 0;
+    if (row < n) {
+        PointRec<T> q = pts[row];
+        int64_t e1 = rp[row + 1];
+        for (int64_t e = rp[row] + sub; e < e1; e += G) {
+            int32_t j = col[e];
+            T p = val[e];
+            if ((uint32_t)j >= (uint64_t)n) {  // malformed CSR: flag it, never read outside
+                atomicOr(err, HTS_ERR_BAD_INDEX);
+                continue;
+            }
+            PointRec<T> o = pts[j];
+            double dd;
+            double t = dist_arg<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, dd);
+            PairTerm<T> r = pair_term<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, t, dd);
+            T coef = (j == row) ? (T)0 : p * r.w * r.base;
+            fx += coef * r.vx;
+            fy += coef * r.vy;
+        }
+    }
+    fx = group_sum<G>(fx);
+    fy = group_sum<G>(fy);
+    if (row < n && sub == 0) {
+        fattr[2 * row] = fx;
+        fattr[2 * row + 1] = fy;
+    }
+}
+
+template <typename T>
+hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, const int64_t *rp,
+                          const int32_t *col, const T *val, int64_t n, T *fattr) {
+    constexpr int G = 16;
+    TimedScope ts(ctx, st, HTS_K_ATTRACT);
+    hipLaunchKernelGGL((k_attract<T, G>), dim3(cdiv(n * G, kBlock)), dim3(kBlock), 0, st, pts, rp,
+                       col, val, n, fattr, ctx->d_err);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
+// ---------------------------------------------------------------- exact
+// Second sum of eq. (15) and Z over all pairs.  A lane owns a query point;
+// the j loop is uniform across the wave, so the other point's record comes
+// through scalar loads.  Short runs of j accumulate in T, then in double.
+// blockIdx.y selects a chunk of j so that enough waves exist to fill the chip.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_exact(const PointRec<T> *__restrict__ pts, int64_t n,
+                                                  int64_t chunk_len, double *__restrict__ part) {
+    constexpr int kRun = 256;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool valid = i < n;
+    PointRec<T> q = pts[valid ? i : 0];
+    int64_t j0 = (int64_t)blockIdx.y * chunk_len;
+    int64_t j1 = j0 + chunk_len < n ? j0 + chunk_len : n;
+    double Fx = 0.0, Fy = 0.0, Z = 0.0;
+    for (int64_t jt = j0; jt < j1; jt += kRun) {
+        int64_t je = jt + kRun < j1 ? jt + kRun : j1;
+        T fx = 0, fy = 0;
+        double z = 0.0;
+        for (int64_t j = jt; j < je; ++j) {
+            PointRec<T> o = pts[j];
+            double dd;
+            double t = dist_arg<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, dd);
+            PairTerm<T> r = pair_term<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, t, dd);
+            bool self = (j == i);
+            T coef = self ? (T)0 : r.w * r.w * r.base;
+            fx += coef * r.vx;
+            fy += coef * r.vy;
+            z += self ? 0.0 : (double)r.w;
+        }
+        Fx += (double)fx;
+        Fy += (double)fy;
+        Z += z;
+    }
+    if (valid) {
+        int64_t o = ((int64_t)blockIdx.y * n + i) * 3;
+        part[o] = Fx;
+        part[o + 1] = Fy;
+        part[o + 2] = Z;
+    }
+}
+
+// per point: sum the chunks in order; per block: partial of Z
+__global__ __launch_bounds__(kBlock) void k_exact_reduce(const double *__restrict__ part, int64_t n,
+                                                         int nchunks, double *__restrict__ frep,
+                                                         double *__restrict__ zpart) {
+    __shared__ double sh[kBlock];
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double z = 0.0;
+    if (i < n) {
+        double fx = 0.0, fy = 0.0;
+        for (int c = 0; c < nchunks; ++c) {
+            int64_t o = ((int64_t)c * n + i) * 3;
+            fx += part[o];
+            fy += part[o + 1];
+            z += part[o + 2];
+        }
+        frep[2 * i] = fx;
+        frep[2 * i + 1] = fy;
+    }
+    sh[threadIdx.x] = z;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) zpart[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,
+                        double *frep, double *zpart, int64_t *nz_out) {
+    int64_t qblocks = cdiv(n, kBlock);
+    // about 8 waves per SIMD on 256 CUs x 4 SIMDs
+    int64_t nchunks = cdiv(8192, qblocks * (kBlock / kWave));
+    if (nchunks < 1) nchunks = 1;
+    if (nchunks > 64) nchunks = 64;
+    if (nchunks > n) nchunks = n;
+    int64_t chunk_len = cdiv(n, nchunks);
+    nchunks = cdiv(n, chunk_len);
+    HTS_OKR(ensure(ctx->part, (size_t)(nchunks * n * 3) * sizeof(double)));
+    double *part = (double *)ctx->part.p;
+    {
+        TimedScope ts(ctx, st, HTS_K_EXACT);
+        hipLaunchKernelGGL(k_exact<T>, dim3(qblocks, nchunks), dim3(kBlock), 0, st, pts, n,
+                           chunk_len, part);
+        HTS_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_exact_reduce, dim3(qblocks), dim3(kBlock), 0, st, part, n, (int)nchunks,
+                       frep, zpart);
+    HTS_HIP(hipGetLastError());
+    *nz_out = qblocks;
+    return HTS_OK;
+}
+
+// ---------------------------------------------------------------- combine
+// Z = sum of the partials in a fixed order (every block repeats the same
+// reduction, so no global synchronisation is needed), then
+// g_i = 4 (a F_attr,i - F_rep,i / Z).
+template <typename T, typename FR>
+__global__ __launch_bounds__(kBlock) void k_finalize(const T *__restrict__ fattr,
+                                                     const FR *__restrict__ frep,
+                                                     const double *__restrict__ zpart, int64_t nz,
+                                                     int64_t n, double ex, T *__restrict__ grad,
+                                                     double *__restrict__ z_dev,
+                                                     uint32_t *__restrict__ err) {
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (int64_t a = threadIdx.x; a < nz; a += kBlock) s += zpart[a];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    double Z = sh[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *z_dev = Z;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double inv = 1.0 / Z;
+    double gx = 4.0 * (ex * (double)fattr[2 * i] - (double)frep[2 * i] * inv);
+    double gy = 4.0 * (ex * (double)fattr[2 * i + 1] - (double)frep[2 * i + 1] * inv);
+    T ox = (T)gx, oy = (T)gy;
+    if (!isfinite(ox) || !isfinite(oy)) atomicOr(err, HTS_ERR_NONFINITE_GRAD);
+    grad[2 * i] = ox;
+    grad[2 * i + 1] = oy;
+}
+
+template <typename T, typename FR>
+hts_status launch_finalize(hts_ctx ctx, hipStream_t st, const T *fattr, const FR *frep,
+                           const double *zpart, int64_t nz, int64_t n, double ex, T *grad,
+                           double *z_dev) {
+    TimedScope ts(ctx, st, HTS_K_FINALIZE);
+    hipLaunchKernelGGL((k_finalize<T, FR>), dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,
+                       zpart, nz, n, ex, grad, z_dev, ctx->d_err);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
+// ---------------------------------------------------------------- step
+// Riemannian step with momentum and gains (eqs. (7), (16)-(18), Sec. 5).
+// State is stored in T; the exponential map, the Mobius addition and the
+// projection run in double.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_step(T *__restrict__ Y, T *__restrict__ U,
+                                                 T *__restrict__ G, const T *__restrict__ grad,
+                                                 int64_t n, double eta, double mu, double min_gain,
+                                                 double eps, int metric_power,
+                                                 uint32_t *__restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double y0 = (double)Y[2 * i], y1 = (double)Y[2 * i + 1];
+    double a = 1.0 - (y0 * y0 + y1 * y1);
+    double s = metric_power == 2 ? a * a * 0.25 : a * 0.5;
+    double u[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        double gh = s * (double)grad[2 * i + c];
+        double uc = (double)U[2 * i + c];
+        double g = (double)G[2 * i + c];
+        g = ((gh > 0.0) != (uc > 0.0)) ? g + 0.2 : g * 0.8;
+        if (g < min_gain) g = min_gain;
+        T gs = (T)g;
+        T us = (T)(mu * uc - eta * (double)gs * gh);
+        G[2 * i + c] = gs;
+        U[2 * i + c] = us;
+        u[c] = (double)us;
+        if (!isfinite(gh)) atomicOr(err, HTS_ERR_NONFINITE_GRAD);
+    }
+    double nv = sqrt(u[0] * u[0] + u[1] * u[1]);
+    double o0 = y0, o1 = y1;
+    if (nv > 0.0) {
+        // exp_y(u) = y (+) tanh(lambda |u| / 2) u / |u|,  lambda = 2 / a
+        double sc = tanh(nv / a) / nv;
+        double b0 = sc * u[0], b1 = sc * u[1];
+        double ab = y0 * b0 + y1 * b1;
+        double aa = y0 * y0 + y1 * y1;
+        double bb = b0 * b0 + b1 * b1;
+        double na = 1.0 + 2.0 * ab + bb;
+        double nb = 1.0 - aa;
+        double den = 1.0 + 2.0 * ab + aa * bb;
+        o0 = (na * y0 + nb * b0) / den;
+        o1 = (na * y1 + nb * b1) / den;
+    }
+    // eq. (18) when |y| >= 1; |y|^2 within 2^-50 of 1 counts as on the circle,
+    // so 1 - |y|^2 of a stored point never rounds to zero
+    constexpr double kOnCircle = 1.0 - 0x1p-50;
+    double q2 = o0 * o0 + o1 * o1;
+    if (q2 >= kOnCircle) {
+        double r = sqrt(q2);
+        o0 = (1.0 - eps) * o0 / r;
+        o1 = (1.0 - eps) * o1 / r;
+    }
+    T s0 = (T)o0, s1 = (T)o1;
+    double r2 = (double)s0 * (double)s0 + (double)s1 * (double)s1;
+    if (r2 >= kOnCircle) {  // the rounded point reached the circle: project the stored value
+        double rr = sqrt(r2);
+        s0 = (T)((1.0 - eps) * (double)s0 / rr);
+        s1 = (T)((1.0 - eps) * (double)s1 / rr);
+    }
+    if (!isfinite(s0) || !isfinite(s1)) atomicOr(err, HTS_ERR_NONFINITE_Y);
+    Y[2 * i] = s0;
+    Y[2 * i + 1] = s1;
+}
+
+template <typename T>
+hts_status launch_step(hts_ctx ctx, hipStream_t st, T *Y, T *U, T *G, const T *grad, int64_t n,
+                       double eta, double mu, double min_gain, double eps, int metric_power) {
+    TimedScope ts(ctx, st, HTS_K_STEP);
+    hipLaunchKernelGGL(k_step<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, Y, U, G, grad, n, eta,
+                       mu, min_gain, eps, metric_power, ctx->d_err);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
+#define HTS_INST(T)                                                                              \
+    template hts_status launch_prep_points<T>(hts_ctx, hipStream_t, const T *, int64_t,           \
+                                              PointRec<T> *);                                    \
+    template hts_status launch_attract<T>(hts_ctx, hipStream_t, const PointRec<T> *,              \
+                                          const int64_t *, const int32_t *, const T *, int64_t,   \
+                                          T *);                                                  \
+    template hts_status launch_exact<T>(hts_ctx, hipStream_t, const PointRec<T> *, int64_t,       \
+                                        double *, double *, int64_t *);                          \
+    template hts_status launch_finalize<T, T>(hts_ctx, hipStream_t, const T *, const T *,         \
+                                              const double *, int64_t, int64_t, double, T *,      \
+                                              double *);                                         \
+    template hts_status launch_step<T>(hts_ctx, hipStream_t, T *, T *, T *, const T *, int64_t,   \
+                                       double, double, double, double, int);
+HTS_INST(float)
+HTS_INST(double)
+template hts_status launch_finalize<float, double>(hts_ctx, hipStream_t, const float *,
+                                                   const double *, const double *, int64_t,
+                                                   int64_t, double, float *, double *);
+
+}  // namespace hts

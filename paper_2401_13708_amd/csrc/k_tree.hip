@@ -1,0 +1,451 @@
+// k_tree.hip -- GPU build of the polar quadtree (Sec. 2-D, Sec. 4-A).
+//
+// The tree is built from sorted (r, phi) keys instead of by insertion:
+//  1. polar position of every point (double, from the single-precision
+//     coordinates) and per-block min/max of r;
+//  2. key of every point: max_depth levels of the split rule, two bits per
+//     level (radial bit: r >= (lo + hi) / 2 of eq. (10); angular bit:
+//     phi >= (lo + hi) / 2), most significant level first;
+//  3. stable radix sort of (key, index);
+//  4. per sorted position: how many nodes start there (from the common
+//     prefixes with both neighbours), the sorted point record and the
+//     Einstein-midpoint summands, with block aggregates;
+//  5. exclusive scans (node offsets; double-double summand sums);
+//  6. node emission in depth-first pre-order: counts, subtree ends, leaves,
+//     midpoints (eq. (11)) and cell diameters.
+// A cell becomes a node when its parent holds two or more points (the same
+// set of cells the insertion build of Sec. 2-D produces), so no insertion
+// order is involved.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "hts_impl.hpp"
+#include "hts_math.hpp"
+
+namespace hts {
+
+constexpr double kTwoPi = 2.0 * 3.14159265358979323846;
+
+// ---------------------------------------------------------------- 1. polar
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_polar(const T *__restrict__ Y, int64_t n,
+                                                  double *__restrict__ r, double *__restrict__ phi,
+                                                  double *__restrict__ mm) {
+    __shared__ double smin[kBlock], smax[kBlock];
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double vmin = __builtin_inf(), vmax = -__builtin_inf();
+    if (i < n) {
+        // position of the single-precision coordinates; products are exact
+        double x = (double)(float)Y[2 * i], y = (double)(float)Y[2 * i + 1];
+        double rr = __dsqrt_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)));
+        double p = atan2(y, x);
+        if (p < 0.0) p = __dadd_rn(p, kTwoPi);
+        r[i] = rr;
+        phi[i] = p;
+        vmin = vmax = rr;
+    }
+    smin[threadIdx.x] = vmin;
+    smax[threadIdx.x] = vmax;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        mm[2 * blockIdx.x] = smin[0];
+        mm[2 * blockIdx.x + 1] = smax[0];
+    }
+}
+
+// ---------------------------------------------------------------- 2. keys
+__global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
+                                                 const double *__restrict__ phi, int64_t n,
+                                                 const double *__restrict__ mm, int nbm, int L,
+                                                 uint64_t *__restrict__ keys,
+                                                 uint32_t *__restrict__ idx,
+                                                 double *__restrict__ root) {
+    __shared__ double smin[kBlock], smax[kBlock];
+    double vmin = __builtin_inf(), vmax = -__builtin_inf();
+    for (int b = threadIdx.x; b < nbm; b += kBlock) {
+        vmin = fmin(vmin, mm[2 * b]);
+        vmax = fmax(vmax, mm[2 * b + 1]);
+    }
+    smin[threadIdx.x] = vmin;
+    smax[threadIdx.x] = vmax;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    double rmin = smin[0], rmax = smax[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        root[0] = rmin;
+        root[1] = rmax;
+    }
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double rv = r[i], pv = phi[i];
+    double lo = rmin, hi = rmax, plo = 0.0, phh = kTwoPi;
+    uint64_t key = 0;
+    for (int l = 0; l < L; ++l) {
+        double mr = __dmul_rn(__dadd_rn(lo, hi), 0.5);
+        double mp = __dmul_rn(__dadd_rn(plo, phh), 0.5);
+        int rb = rv >= mr, pb = pv >= mp;
+        key = (key << 2) | (uint64_t)(2 * rb + pb);
+        if (rb) lo = mr; else hi = mr;
+        if (pb) plo = mp; else phh = mp;
+    }
+    keys[i] = key;
+    idx[i] = (uint32_t)i;
+}
+
+// number of equal leading levels of two keys
+__device__ __forceinline__ int lcp_levels(uint64_t a, uint64_t b, int L) {
+    uint64_t x = a ^ b;
+    if (x == 0) return L;
+    return (__clzll((long long)x) - (64 - 2 * L)) >> 1;
+}
+
+// nodes starting at sorted position i: depths s..D with s = lcp(i-1, i) + 1
+// (0 for i = 0) and D = min(L, max(lcp with either neighbour) + 1), the depth
+// at which the point's cell holds it alone (or the depth cap).
+struct NodeSpan { int s, D; };
+__device__ __forceinline__ NodeSpan node_span(const uint64_t *__restrict__ keys, int64_t i, int64_t n,
+                                              int L) {
+    uint64_t k = keys[i];
+    int lcpl = i > 0 ? lcp_levels(keys[i - 1], k, L) : -1;
+    int lcpr = i + 1 < n ? lcp_levels(k, keys[i + 1], L) : -1;
+    int mx = lcpl > lcpr ? lcpl : lcpr;
+    NodeSpan sp;
+    sp.D = mx + 1 < L ? mx + 1 : L;
+    sp.s = i > 0 ? lcpl + 1 : 0;
+    return sp;
+}
+
+// ---------------------------------------------------------------- 4. sorted
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sorted(const T *__restrict__ Y, int64_t n,
+                                                   const uint64_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ perm, int L,
+                                                   PointRec<T> *__restrict__ spts,
+                                                   int32_t *__restrict__ cnt,
+                                                   DD3 *__restrict__ q,
+                                                   int32_t *__restrict__ cnt_part,
+                                                   DD3 *__restrict__ q_part) {
+    __shared__ int scnt[kBlock];
+    __shared__ DD3 sq[kBlock];
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int c = 0;
+    DD3 v = dd_zero();
+    if (i < n) {
+        uint32_t p = perm[i];
+        T x = Y[2 * p], y = Y[2 * p + 1];
+        double xd = (double)x, yd = (double)y;
+        double r2 = xd * xd + yd * yd;
+        double a = 1.0 - r2;
+        PointRec<T> pr;
+        pr.x = x;
+        pr.y = y;
+        pr.ia = 1.0 / a;
+        if constexpr (sizeof(T) == 8) pr.pad = 0.0;
+        spts[i] = pr;
+        // Klein coordinates v = 2y / (1 + |y|^2) with gamma(v) = (1 + |y|^2) / (1 - |y|^2):
+        // gamma v = lambda y, the summands of eq. (11)
+        double lam = 2.0 / a;
+        v.hi[0] = lam * xd;
+        v.hi[1] = lam * yd;
+        v.hi[2] = (1.0 + r2) / a;
+        NodeSpan sp = node_span(keys, i, n, L);
+        c = sp.D - sp.s + 1;
+        if (c < 0) c = 0;
+        cnt[i] = c;
+        q[i] = v;
+    }
+    scnt[threadIdx.x] = c;
+    sq[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            scnt[threadIdx.x] += scnt[threadIdx.x + s];
+            sq[threadIdx.x] = dd_add(sq[threadIdx.x], sq[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cnt_part[blockIdx.x] = scnt[0];
+        q_part[blockIdx.x] = sq[0];
+    }
+}
+
+// ---------------------------------------------------------------- 5. scans
+// one block: exclusive scan of the block aggregates; writes the totals
+__global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt_part,
+                                                       DD3 *__restrict__ q_part, int64_t nb,
+                                                       int32_t *__restrict__ node_start,
+                                                       DD3 *__restrict__ psum, int64_t n,
+                                                       int32_t *__restrict__ d_m, int64_t cap,
+                                                       uint32_t *__restrict__ err) {
+    __shared__ int scnt[kBlock];
+    __shared__ DD3 sq[kBlock];
+    int64_t per = cdiv(nb, kBlock);
+    int64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+    int c = 0;
+    DD3 v = dd_zero();
+    for (int64_t b = b0; b < b1; ++b) {
+        c += cnt_part[b];
+        v = dd_add(v, q_part[b]);
+    }
+    scnt[threadIdx.x] = c;
+    sq[threadIdx.x] = v;
+    __syncthreads();
+    // inclusive Hillis-Steele scan over the thread totals
+    for (int o = 1; o < kBlock; o <<= 1) {
+        int ca = 0;
+        DD3 va = dd_zero();
+        bool take = (int)threadIdx.x >= o;
+        if (take) {
+            ca = scnt[threadIdx.x - o];
+            va = sq[threadIdx.x - o];
+        }
+        __syncthreads();
+        if (take) {
+            scnt[threadIdx.x] += ca;
+            sq[threadIdx.x] = dd_add(va, sq[threadIdx.x]);
+        }
+        __syncthreads();
+    }
+    int ex_c = threadIdx.x > 0 ? scnt[threadIdx.x - 1] : 0;
+    DD3 ex_v = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd_zero();
+    for (int64_t b = b0; b < b1; ++b) {
+        int cb = cnt_part[b];
+        DD3 vb = q_part[b];
+        cnt_part[b] = ex_c;
+        q_part[b] = ex_v;
+        ex_c += cb;
+        ex_v = dd_add(ex_v, vb);
+    }
+    if (threadIdx.x == kBlock - 1) {
+        int m = scnt[kBlock - 1];
+        if (m > cap) {
+            atomicOr(err, HTS_ERR_TREE_OVERFLOW);
+            m = (int)cap;
+        }
+        node_start[n] = m;
+        psum[n] = sq[kBlock - 1];
+        *d_m = m;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t *__restrict__ cnt,
+                                                       DD3 *__restrict__ q, int64_t n,
+                                                       const int32_t *__restrict__ cnt_part,
+                                                       const DD3 *__restrict__ q_part) {
+    __shared__ int scnt[kBlock];
+    __shared__ DD3 sq[kBlock];
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    scnt[threadIdx.x] = i < n ? cnt[i] : 0;
+    sq[threadIdx.x] = i < n ? q[i] : dd_zero();
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        int ca = 0;
+        DD3 va = dd_zero();
+        bool take = (int)threadIdx.x >= o;
+        if (take) {
+            ca = scnt[threadIdx.x - o];
+            va = sq[threadIdx.x - o];
+        }
+        __syncthreads();
+        if (take) {
+            scnt[threadIdx.x] += ca;
+            sq[threadIdx.x] = dd_add(va, sq[threadIdx.x]);
+        }
+        __syncthreads();
+    }
+    if (i < n) {
+        int ex_c = threadIdx.x > 0 ? scnt[threadIdx.x - 1] : 0;
+        DD3 ex_v = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd_zero();
+        cnt[i] = cnt_part[blockIdx.x] + ex_c;
+        q[i] = dd_add(q_part[blockIdx.x], ex_v);
+    }
+}
+
+// ---------------------------------------------------------------- 6. nodes
+__device__ __forceinline__ double dd_diff(const DD3 &a, const DD3 &b, int c) {
+    double s, e;
+    two_sum(a.hi[c], -b.hi[c], s, e);
+    e += a.lo[c] - b.lo[c];
+    return s + e;
+}
+
+// first position j > i whose key differs from keys[i] in the first l levels
+__device__ __forceinline__ int64_t cell_end(const uint64_t *__restrict__ keys, int64_t i, int64_t n,
+                                            int l, int L) {
+    int sh = 2 * (L - l);
+    uint64_t pre = sh >= 64 ? 0 : (keys[i] >> sh);
+    int64_t lo = i + 1, hi = n;  // answer in [lo, hi]
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        uint64_t pm = sh >= 64 ? 0 : (keys[mid] >> sh);
+        if (pm == pre) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ keys, int64_t n, int L,
+                                                 const PointRec<T> *__restrict__ spts,
+                                                 const int32_t *__restrict__ node_start,
+                                                 const DD3 *__restrict__ psum,
+                                                 const double *__restrict__ root,
+                                                 const double *__restrict__ sinhalf,
+                                                 NodeRec<T> *__restrict__ nodes,
+                                                 double *__restrict__ r_cell,
+                                                 int32_t *__restrict__ node_first,
+                                                 int64_t cap, uint32_t *__restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    NodeSpan sp = node_span(keys, i, n, L);
+    if (sp.D < sp.s) return;
+    int32_t M = node_start[n];
+    int32_t base = node_start[i];
+    uint64_t key = keys[i];
+    double lo = root[0], hi = root[1];
+    int lev = 0;  // levels replayed into (lo, hi)
+    for (int l = sp.s; l <= sp.D; ++l) {
+        int32_t k = base + (l - sp.s);
+        if (k >= cap) {  // cannot happen for a consistent scan; never write past the storage
+            atomicOr(err, HTS_ERR_TREE_OVERFLOW);
+            return;
+        }
+        bool leaf = (l == sp.D);
+        int64_t end = (leaf && l < L) ? i + 1 : cell_end(keys, i, n, l, L);
+        int32_t count = (int32_t)(end - i);
+        int32_t next = end < n ? node_start[end] : M;
+        NodeRec<T> rec;
+        rec.count = count;
+        rec.next_depth = (uint32_t)next | ((uint32_t)l << kNextBits);
+        if constexpr (sizeof(T) == 8) rec.pad = 0.0;
+        if (leaf && count == 1) {
+            PointRec<T> p = spts[i];
+            rec.mx = p.x;
+            rec.my = p.y;
+            rec.ib = p.ia;
+        } else {
+            // Einstein midpoint, eq. (11): Klein average then back to the disk
+            DD3 se = psum[end], si = psum[i];
+            double sx = dd_diff(se, si, 0), sy = dd_diff(se, si, 1), sg = dd_diff(se, si, 2);
+            double kx = sx / sg, ky = sy / sg;
+            double den = 1.0 + sqrt(fmax(0.0, 1.0 - (kx * kx + ky * ky)));
+            T mx = (T)(kx / den), my = (T)(ky / den);
+            rec.mx = mx;
+            rec.my = my;
+            rec.ib = 1.0 / (1.0 - ((double)mx * (double)mx + (double)my * (double)my));
+        }
+        rec.c = leaf ? __longlong_as_double((long long)i) : 0.0;
+        nodes[k] = rec;
+        node_first[k] = (int32_t)i;
+        // radial bounds of the cell (same arithmetic as the keys)
+        while (lev < l) {
+            int rb = (int)((key >> (2 * (L - 1 - lev) + 1)) & 1u);
+            double mr = __dmul_rn(__dadd_rn(lo, hi), 0.5);
+            if (rb) lo = mr; else hi = mr;
+            ++lev;
+        }
+        // hyperbolic diameter: the larger of the outer-arc chord and the
+        // diagonal (the radial edge is never longer than the diagonal); the
+        // angular half-width is capped at pi/2 for the two top levels
+        double s = sinhalf[l];
+        double ahi = 1.0 - hi * hi, alo = 1.0 - lo * lo;
+        double t_outer = 8.0 * hi * hi * s * s / (ahi * ahi);
+        double dr = hi - lo;
+        double t_diag = 2.0 * (dr * dr + 4.0 * lo * hi * s * s) / (alo * ahi);
+        double t = fmax(t_outer, t_diag);
+        r_cell[k] = log1p(t + sqrt(t * (t + 2.0)));
+    }
+}
+
+// criterion threshold per internal node: r_cell / d < theta  <=>  t > cosh(r_cell / theta) - 1
+// = 2 sinh^2(r_cell / (2 theta)) (the sinh form keeps small thresholds accurate)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_threshold(NodeRec<T> *__restrict__ nodes,
+                                                      const double *__restrict__ r_cell,
+                                                      const int32_t *__restrict__ d_m,
+                                                      double theta) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= *d_m) return;
+    uint32_t next = nodes[k].next_depth & kNextMask;
+    if ((int64_t)next == k + 1) return;  // leaf
+    double c;
+    if (theta > 0.0) {
+        double sh = sinh(r_cell[k] / (2.0 * theta));
+        c = 2.0 * sh * sh;
+    } else {
+        c = __builtin_inf();
+    }
+    nodes[k].c = c;
+}
+
+template <typename T>
+hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tree t) {
+    TimedScope ts(ctx, st, HTS_K_TREE);
+    const int L = t->max_depth;
+    const int64_t nb = cdiv(n, kBlock);
+    hipLaunchKernelGGL(k_polar<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->r, t->phi, t->mm);
+    HTS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kBlock), 0, st, t->r, t->phi, n, t->mm, (int)nb, L,
+                       t->keys_in, t->idx_in, t->root);
+    HTS_HIP(hipGetLastError());
+    size_t bytes = t->sort_tmp_bytes;
+    HTS_HIP(rocprim::radix_sort_pairs(t->sort_tmp, bytes, t->keys_in, t->keys, t->idx_in, t->perm,
+                                      (size_t)n, 0u, (unsigned)(2 * L), st));
+    hipLaunchKernelGGL(k_sorted<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->keys, t->perm, L,
+                       (PointRec<T> *)t->spts, t->node_start, t->psum, t->ncnt_part, t->q_part);
+    HTS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, st, t->ncnt_part, t->q_part, nb,
+                       t->node_start, t->psum, n, t->d_m, t->cap_nodes, ctx->d_err);
+    HTS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, st, t->node_start, t->psum, n,
+                       t->ncnt_part, t->q_part);
+    HTS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_emit<T>, dim3(nb), dim3(kBlock), 0, st, t->keys, n, L,
+                       (const PointRec<T> *)t->spts, t->node_start, t->psum, t->root, t->sinhalf,
+                       (NodeRec<T> *)t->nodes, t->r_cell, t->node_first, t->cap_nodes,
+                       ctx->d_err);
+    HTS_HIP(hipGetLastError());
+    t->n = n;
+    t->dtype = sizeof(T) == 8 ? HTS_F64 : HTS_F32;
+    return HTS_OK;
+}
+
+hts_status tree_sort_bytes(int64_t n_max, int L, size_t *bytes) {
+    *bytes = 0;
+    HTS_HIP(rocprim::radix_sort_pairs(nullptr, *bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                      (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n_max, 0u,
+                                      (unsigned)(2 * L), (hipStream_t)0));
+    return HTS_OK;
+}
+
+hts_status tree_thresholds(hts_ctx ctx, hipStream_t st, hts_tree t, int dtype, double theta) {
+    int64_t nbm = cdiv(t->cap_nodes, kBlock);
+    // launch over the capacity; the kernel reads the live node count itself
+    int64_t bound = cdiv(t->n * (t->max_depth + 1) + 1, kBlock);
+    if (bound < nbm) nbm = bound;
+    if (dtype == HTS_F64)
+        hipLaunchKernelGGL(k_threshold<double>, dim3(nbm), dim3(kBlock), 0, st,
+                           (NodeRec<double> *)t->nodes, t->r_cell, t->d_m, theta);
+    else
+        hipLaunchKernelGGL(k_threshold<float>, dim3(nbm), dim3(kBlock), 0, st,
+                           (NodeRec<float> *)t->nodes, t->r_cell, t->d_m, theta);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
+template hts_status tree_build<float>(hts_ctx, hipStream_t, const float *, int64_t, hts_tree);
+template hts_status tree_build<double>(hts_ctx, hipStream_t, const double *, int64_t, hts_tree);
+
+}  // namespace hts

@@ -135,22 +135,21 @@ def disk_state(n: int, stage: str = "mid", n_clusters: int = 10,
 
 
 def random_csr(n: int, k: int = 90, seed: int = 11, dtype=np.float32):
-    """Row structure of a symmetrised k-NN graph (row lengths in [k, 2k]),
-    random positive values normalised to sum 1.  Timing inputs only."""
+    """Row structure of a symmetrised k-NN graph (about k to 2k entries per
+    row, columns ascending, no diagonal), random positive values normalised
+    to sum 1.  For inputs whose only role is their sparsity shape."""
     g = rng(seed)
-    extra = g.integers(0, k + 1, size=n)
-    lens = k + extra
+    lens = k + g.integers(0, k + 1, size=n)
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    cols = g.integers(0, n - 1, size=rows.size)
+    cols = cols + (cols >= rows)                    # skip the diagonal
+    key = np.unique(rows * n + cols)                # sorted, duplicates removed
+    rows, cols = key // n, key % n
     row_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(lens, out=row_ptr[1:])
-    nnz = int(row_ptr[-1])
-    col = np.empty(nnz, dtype=np.int32)
-    for i in range(n):
-        c = g.choice(n - 1, size=lens[i], replace=False)
-        c[c >= i] += 1
-        col[row_ptr[i]:row_ptr[i + 1]] = np.sort(c)
-    val = g.random(nnz)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    val = g.random(cols.size)
     val /= val.sum()
-    return row_ptr, col, val.astype(dtype)
+    return row_ptr, cols.astype(np.int32), val.astype(dtype)
 
 
 def subsample(n: int, m: int, seed: int = 99) -> np.ndarray:

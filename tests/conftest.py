@@ -10,3 +10,11 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    from paper_2401_13708_amd import hts
+    c = hts.Context(0)
+    yield c
+    c.close()

@@ -1,0 +1,29 @@
+"""Shared seeded inputs for the GPU parity tests (generators and oracle only)."""
+import functools
+
+import numpy as np
+
+import oracle
+from paper_2401_13708_amd import synth
+
+STAGES = ["init", "early", "mid", "late", "edge"]
+
+
+@functools.lru_cache(maxsize=None)
+def affinities(n: int, d: int = 32, perplexity: float = 30.0, k: int = 90, seed: int = 1):
+    """P of a Gaussian mixture, built by the oracle (shared by both sides)."""
+    X = synth.gaussian_mixture(n, d, seed=seed)
+    k = min(k, n - 1)
+    perplexity = min(perplexity, k / 3.0)
+    knn, rp, col, val = oracle.build_affinities(X, perplexity, k)
+    return X, knn, rp, col, val
+
+
+def embedding(n: int, stage: str, dtype, seed: int = 5):
+    return synth.disk_state(n, stage, seed=seed, dtype=dtype)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))

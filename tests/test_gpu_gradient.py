@@ -1,0 +1,144 @@
+"""GPU gradients against the FP64 oracle on shared seeded inputs.
+
+Bars: double-precision instantiation within 1e-10 (rounding order only);
+single precision: exact gradient relative L2 <= 1e-4, Barnes-Hut gradient
+relative L2 <= 1e-3 against the oracle's Barnes-Hut at the same theta, Z
+relative <= 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2401_13708_amd import hts
+from gpu_inputs import STAGES, affinities, embedding, rel
+
+pytestmark = pytest.mark.gpu
+
+DT = {np.float32: torch.float32, np.float64: torch.float64}
+
+
+def _dev(a, dtype=None):
+    return torch.from_numpy(np.ascontiguousarray(a if dtype is None else a.astype(dtype))).cuda()
+
+
+def _run_exact(ctx, Y, rp, col, val, ex):
+    g, z = hts.gradient_exact(ctx, _dev(Y), _dev(rp), _dev(col), _dev(val), ex)
+    torch.cuda.synchronize()
+    assert ctx.check() == 0
+    return g.cpu().numpy(), float(z.cpu()[0])
+
+
+def _run_bh(ctx, Y, rp, col, val, ex, theta, max_depth=20, stats=False):
+    Yd = _dev(Y)
+    tree = hts.Tree(ctx, Y.shape[0], max_depth)
+    hts.build_polar_tree(ctx, Yd, tree)
+    st = torch.zeros(3, dtype=torch.int64, device="cuda") if stats else None
+    g, z = hts.gradient_bh(ctx, Yd, _dev(rp), _dev(col), _dev(val), tree, theta, ex, stats=st)
+    torch.cuda.synchronize()
+    assert ctx.check() == 0
+    out = (g.cpu().numpy(), float(z.cpu()[0]))
+    if stats:
+        out = out + (st.cpu().numpy().tolist(),)
+    tree.close()
+    return out
+
+
+@pytest.mark.parametrize("stage", STAGES)
+@pytest.mark.parametrize("ex", [12.0, 1.0])
+def test_exact_f64(ctx, stage, ex):
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, stage, np.float64)
+    g, z = _run_exact(ctx, Y, rp, col, val, ex)
+    go, zo = oracle.gradient_exact(Y, rp, col, val, ex)
+    assert rel(g, go) < 1e-10
+    assert z == pytest.approx(zo, rel=1e-12)
+
+
+@pytest.mark.parametrize("stage", STAGES)
+@pytest.mark.parametrize("n", [1000, 1337])
+def test_exact_f32(ctx, stage, n):
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, stage, np.float32)
+    v32 = val.astype(np.float32)
+    g, z = _run_exact(ctx, Y, rp, col, v32, 12.0)
+    go, zo = oracle.gradient_exact(Y.astype(np.float64), rp, col, v32.astype(np.float64), 12.0)
+    assert rel(g, go) < 1e-4
+    assert z == pytest.approx(zo, rel=1e-5)
+
+
+@pytest.mark.parametrize("n", [2, 3, 65, 257])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_exact_small_sizes(ctx, n, dtype):
+    X, _, rp, col, val = affinities(n, d=4, k=min(90, n - 1))
+    Y = embedding(n, "mid", dtype)
+    g, z = _run_exact(ctx, Y, rp, col, val.astype(dtype), 1.0)
+    go, zo = oracle.gradient_exact(Y.astype(np.float64), rp, col, val.astype(dtype).astype(np.float64))
+    if n == 2:
+        # p_12 = q_12 = 1/2: attraction and repulsion cancel exactly
+        assert np.abs(g).max() < (1e-6 if dtype == np.float32 else 1e-14)
+        assert np.abs(go).max() < 1e-14
+    else:
+        assert rel(g, go) < (1e-4 if dtype == np.float32 else 1e-10)
+    assert z == pytest.approx(zo, rel=1e-5 if dtype == np.float32 else 1e-12)
+
+
+@pytest.mark.parametrize("stage", STAGES)
+def test_bh_theta0_equals_exact(ctx, stage):
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, stage, np.float64)
+    g, z, st = _run_bh(ctx, Y, rp, col, val, 12.0, 0.0, stats=True)
+    go, zo = oracle.gradient_exact(Y, rp, col, val, 12.0)
+    assert rel(g, go) < 1e-10
+    assert z == pytest.approx(zo, rel=1e-12)
+    assert st[1] == 0 and st[2] == 1000 * 999
+
+
+@pytest.mark.parametrize("stage", STAGES)
+def test_bh_f64_matches_oracle_bh(ctx, stage):
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, stage, np.float64)
+    g, z, st = _run_bh(ctx, Y, rp, col, val, 1.0, 0.5, stats=True)
+    t = oracle.Tree(Y)
+    go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 1.0)
+    assert st == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    assert rel(g, go) < 1e-10
+    # an accepted cell's midpoint carries the rounding of its sums, amplified
+    # by 1 / (1 - |m|^2) near the rim
+    assert z == pytest.approx(zo, rel=1e-10)
+
+
+@pytest.mark.parametrize("stage", STAGES)
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.8])
+def test_bh_f32_matches_oracle_bh(ctx, stage, theta):
+    n = 1337
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, stage, np.float32)
+    v32 = val.astype(np.float32)
+    g, z = _run_bh(ctx, Y, rp, col, v32, 12.0, theta)
+    Yo = Y.astype(np.float64)
+    t = oracle.Tree(Yo)
+    go, zo, _ = oracle.gradient_bh(Yo, rp, col, v32.astype(np.float64), t, theta, 12.0)
+    assert rel(g, go) < 1e-3
+    assert z == pytest.approx(zo, rel=1e-5)
+
+
+def test_bh_duplicates_and_depth_cap(ctx):
+    n = 600
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, "late", np.float64)
+    Y[10:40] = Y[5]        # 31 identical points share one deepest leaf
+    Y[100] = Y[101]
+    for depth in (20, 6):
+        g, z = _run_bh(ctx, Y, rp, col, val, 1.0, 0.0, max_depth=depth)
+        go, zo = oracle.gradient_exact(Y, rp, col, val, 1.0)
+        assert rel(g, go) < 1e-10
+        assert z == pytest.approx(zo, rel=1e-12)
+
+
+def test_bh_is_deterministic(ctx):
+    n = 1337
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, "mid", np.float32)
+    a = _run_bh(ctx, Y, rp, col, val.astype(np.float32), 1.0, 0.5)
+    b = _run_bh(ctx, Y, rp, col, val.astype(np.float32), 1.0, 0.5)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]

@@ -1,0 +1,64 @@
+"""The C-ABI library loads, exports every function include/hts.h declares,
+and validates arguments on the host before touching the device."""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+from paper_2401_13708_amd import hts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_function():
+    names = hts.header_functions()
+    assert len(names) >= 14
+    L = hts.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", hts.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    for n in names:
+        assert " T %s\n" % n in out, n
+    assert set(hts._SIGS) == set(names)
+
+
+def test_library_is_gfx950_code():
+    # the fat binary carries a code object for the gfx950 target only
+    blob = open(hts.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+    assert b"amdgcn-amd-amdhsa--gfx942" not in blob
+
+
+@pytest.mark.parametrize("call,msg", [
+    (lambda L: L.hts_gradient_bh(None, None, None, 1, 0, None, None, None, 1.0, None, 0.5, None,
+                                 None, None), "n = 1 < 2"),
+    (lambda L: L.hts_gradient_exact(None, None, C.c_void_p(8), 10, 7, C.c_void_p(8),
+                                    C.c_void_p(8), C.c_void_p(8), 1.0, C.c_void_p(8),
+                                    C.c_void_p(8)), "bad dtype"),
+    (lambda L: L.hts_gradient_exact(None, None, C.c_void_p(8), 10, 0, C.c_void_p(8),
+                                    C.c_void_p(8), C.c_void_p(8), 0.0, C.c_void_p(8),
+                                    C.c_void_p(8)), "exaggeration"),
+    (lambda L: L.hts_gradient_bh(None, None, C.c_void_p(8), 10, 0, C.c_void_p(8), C.c_void_p(8),
+                                 C.c_void_p(8), 1.0, C.c_void_p(8), -0.5, C.c_void_p(8),
+                                 C.c_void_p(8), None), "ctx is NULL"),
+    (lambda L: L.hts_step(None, None, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                          10, 0, -1.0, 0.5, 0.01, 1e-5, 2), "eta"),
+    (lambda L: L.hts_step(None, None, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                          10, 0, 1.0, 0.5, 0.01, 1e-5, 3), "metric_power"),
+    (lambda L: L.hts_build_affinities(None, None, C.c_void_p(8), 100, 5, 0, 40.0, 30, None,
+                                      C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), 0, 100,
+                                      C.byref(C.c_int64())), "perplexity"),
+    (lambda L: L.hts_build_affinities(None, None, C.c_void_p(8), 100, 5, 0, 10.0, 100, None,
+                                      C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), 0, 100,
+                                      C.byref(C.c_int64())), "not in [1, n)"),
+    (lambda L: L.hts_tree_create(None, 1, 20, C.byref(C.c_void_p())), "n_max < 2"),
+    (lambda L: L.hts_tree_create(None, 100, 40, C.byref(C.c_void_p())), "max_depth"),
+    (lambda L: L.hts_build_polar_tree(None, None, None, 10, 0, None), "NULL handle"),
+])
+def test_host_validation(call, msg):
+    L = hts.lib()
+    rc = call(L)
+    assert rc == -1
+    assert msg in hts.last_error()
