@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Barnes-Hut hyperbolic t-SNE iterations per second on one MI355X.
+
+Workload: N = 70000 points, D = 784, values in (0, 1) from a 10-class rank-20
+sigmoid factor model (a synthetic stand-in for the 70k x 784 digit data of the
+paper's Table 1); perplexity 30, k = 90; polar-quadtree Barnes-Hut at
+theta = 0.5; the schedule of Sec. 5 (250 iterations with exaggeration 12 and
+momentum 0.5, then momentum 0.8), single-precision forces.  A step is one
+whole iteration: tree build + Barnes-Hut gradient + Riemannian step, inputs
+resident in HBM.  The affinities P are built once on the GPU before timing.
+
+Prints one JSON line.  The exact O(N^2) gradient is timed beside it at the
+same N, and the FP64 CPU oracle on the host cores as the CPU baseline.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BH gradient iters/sec at N=70k θ=0.5 vs exact; jobs/sec + p50/p99 job latency"
+HBM_PEAK_GBS = 8000.0
+# Non-packed FP32 / FP64 vector rate: 256 CU x 64 lanes x 2.4 GHz x 2 (FMA)
+VALU_PEAK_TFLOPS = 78.6
+# Algorithmic flops of the Barnes-Hut traversal: a criterion
+# test computes t = 2|y-m|^2 ia ib and compares (9 flops); an interaction
+# (accepted cell or leaf point) adds sinh d, d, w, the force factor, the
+# direction vector and the three accumulations (26 flops).
+F_TEST, F_PAIR = 9, 26
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def _src_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2401_13708_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {"traverse": ["k_bh.hip", "hts_math.hpp", "hts_impl.hpp"],
+                  "attract": ["k_grad.hip", "hts_math.hpp", "hts_impl.hpp"],
+                  "tree": ["k_tree.hip", "hts_math.hpp", "hts_impl.hpp"]}
+
+
+def _traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if the
+    kernel's sources are unchanged since the counters were taken."""
+    path = os.path.join(PROFILE_DIR, "traffic_%s.json" % kernel)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != _src_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n, seconds, theta):
+    import numpy as np
+    import oracle
+    from paper_2401_13708_amd import synth
+    rp, col, val = synth.random_csr(n, 90, seed=11, dtype=np.float64)
+    Y = synth.disk_state(n, "mid", seed=7).astype(np.float64)
+    U = np.zeros_like(Y)
+    G = np.ones_like(Y)
+    cores = oracle.get_threads()
+    it = 0
+    t0 = time.perf_counter()
+    while True:
+        t = oracle.Tree(Y)
+        g, z, _ = oracle.gradient_bh(Y, rp, col, val, t, theta, 12.0)
+        Y, U, G = oracle.step(Y, U, G, g, n / 12000.0, 0.5)
+        del t
+        it += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": it / el, "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": "%d full iterations (polar quadtree by insertion + Barnes-Hut gradient at "
+                      "theta=%.1f + step) of the FP64 oracle at N=%d on a synthetic clustered "
+                      "embedding with a k-NN-shaped random P (nnz=%d), %.1f s, OpenMP over "
+                      "queries" % (it, theta, n, int(rp[-1]), el)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=990)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=70000)
+    ap.add_argument("--d", type=int, default=784)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--exact-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-events", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for PMC calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d (WORLD_SIZE %s) is not "
+              "supported (the multi-GPU sharding is described in DESIGN.md, not built)"
+              % (args.gpus, os.environ.get("WORLD_SIZE", "1")), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2401_13708_amd import hts, synth
+    from paper_2401_13708_amd.embed import Embedding
+
+    dev = torch.device("cuda", 0)
+    n, d = args.n, args.d
+    t0 = time.perf_counter()
+    X = synth.sigmoid_factor_mixture(n, d, seed=2)
+    Y0 = synth.disk_uniform(n, 1e-4, seed=2 + 10 ** 6)
+    gen_s = time.perf_counter() - t0
+    print("bench: generated X %dx%d in %.1fs" % (n, d, gen_s), file=sys.stderr, flush=True)
+
+    ctx = hts.Context(0)
+    Xd = torch.from_numpy(X).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rp, col, val = hts.build_affinities(ctx, Xd, 30.0, 90, p_dtype=torch.float32, want_knn=False)
+    torch.cuda.synchronize()
+    aff_s = time.perf_counter() - t0
+    nnz = int(col.numel())
+    del Xd
+    print("bench: affinities nnz=%d in %.2fs" % (nnz, aff_s), file=sys.stderr, flush=True)
+
+    emb = Embedding(ctx, rp, col, val, torch.from_numpy(Y0).to(dev), theta=args.theta)
+    for _ in range(args.warmup):
+        emb.iterate()
+    torch.cuda.synchronize()
+    if ctx.check() != 0:
+        raise RuntimeError("device error word set during warm-up")
+    print("bench: warm-up %d iterations done" % args.warmup, file=sys.stderr, flush=True)
+
+    stats = torch.zeros(3, dtype=torch.int64, device=dev)
+    ctx.timing(not args.no_kernel_events)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        emb.iterate(stats)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = e0.elapsed_time(e1)
+    kt = ctx.timing_read()
+    ctx.timing(False)
+    bits = ctx.check()
+    if bits:
+        raise RuntimeError("device error word 0x%x in the timed region" % bits)
+    ms_step = ms_total / args.steps
+    value = 1000.0 / ms_step
+    st = stats.cpu().numpy().tolist()
+    rmax = float(torch.linalg.vector_norm(emb.Y.double(), dim=1).max())
+    print("bench: BH %d steps %.3f ms/step (wall %.2fs) stats=%s rmax=%.6f"
+          % (args.steps, ms_step, wall, st, rmax), file=sys.stderr, flush=True)
+
+    # exact O(N^2) gradient + step at the same N, from the same state
+    exact_ips = None
+    if args.exact_steps > 0:
+        ex = Embedding(ctx, rp, col, val, emb.Y, exact=True)
+        ex.update.copy_(emb.update)
+        ex.gains.copy_(emb.gains)
+        ex.it = emb.it
+        ex.iterate()
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record()
+        for _ in range(args.exact_steps):
+            ex.iterate()
+        f1.record()
+        torch.cuda.synchronize()
+        exact_ips = 1000.0 * args.exact_steps / f0.elapsed_time(f1)
+        ex.close()
+        print("bench: exact %.3f ms/step" % (1000.0 / exact_ips), file=sys.stderr, flush=True)
+
+    if args.copy_calibration_mib > 0:
+        m = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(m, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # roofline of the dominant kernel of the timed region
+    launches = {k: v[1] for k, v in kt.items()}
+    kms = {k: v[0] for k, v in kt.items()}
+    dom = max(("tree", "attract", "traverse", "finalize", "step"), key=lambda k: kms.get(k, 0.0))
+    roof = None
+    if launches.get(dom, 0) > 0:
+        avg_s = kms[dom] / launches[dom] / 1000.0
+        if dom == "traverse":
+            flops = (st[0] * F_TEST + (st[1] + st[2]) * F_PAIR) / launches[dom]
+            ach = flops / avg_s / 1e12
+            roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),
+                    "traffic": _traffic("traverse"), "kernel": "k_traverse",
+                    "avg_launch_us": round(avg_s * 1e6, 2)}
+        else:
+            if dom == "attract":
+                byts = 8.0 * nnz + 8.0 * (n + 1) + 16.0 * n + 8.0 * n
+            else:  # tree build, finalize, step: bytes they must move
+                byts = {"tree": 8.0 * n + 16 * n + 2 * 5 * 12.0 * n + 16 * n + 48.0 * 2 * n,
+                        "finalize": 24.0 * n, "step": 56.0 * n}[dom]
+            ach = byts / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": _traffic(dom) if dom in KERNEL_SOURCES else None,
+                    "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle for ~%.0fs" % args.cpu_seconds, file=sys.stderr, flush=True)
+        cpu = cpu_baseline(n, args.cpu_seconds, args.theta)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "hyperbolic t-SNE Barnes-Hut iteration, N=%d D=%d sigmoid factor "
+                               "mixture, perplexity 30, k=90, theta=%.2f, iterations %d-%d of the "
+                               "1000-iteration schedule" % (n, d, args.theta, args.warmup,
+                                                            args.warmup + args.steps - 1),
+                   "n": n, "d": d, "theta": args.theta, "perplexity": 30, "k": 90, "nnz": nnz},
+        "exact_iters_per_s": round(exact_ips, 3) if exact_ips else None,
+        "speedup_vs_exact": round(value / exact_ips, 1) if exact_ips else None,
+        "kernel_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kt.items() if v[1]},
+        "bh_counts_per_step": {"tests": st[0] // max(1, args.steps),
+                               "accepted_cells": st[1] // max(1, args.steps),
+                               "leaf_pairs": st[2] // max(1, args.steps)},
+        "setup_s": {"generate": round(gen_s, 2), "affinities_gpu": round(aff_s, 3)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paper_context": {"accelerated_s_per_iter": 4.57, "exact_s_per_iter": 191.0,
+                          "dataset": "MNIST 70000x784", "hardware": "CPU, unstated"},
+    }
+    emb.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
