@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-events", action="store_true")
+    ap.add_argument("--no-stats", action="store_true", help="time without traversal counters")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for PMC calibration)")
     args = ap.parse_args()
@@ -140,7 +141,7 @@ def main():
         raise RuntimeError("device error word set during warm-up")
     print("bench: warm-up %d iterations done" % args.warmup, file=sys.stderr, flush=True)
 
-    stats = torch.zeros(3, dtype=torch.int64, device=dev)
+    stats = None if args.no_stats else torch.zeros(5, dtype=torch.int64, device=dev)
     ctx.timing(not args.no_kernel_events)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -159,7 +160,7 @@ def main():
         raise RuntimeError("device error word 0x%x in the timed region" % bits)
     ms_step = ms_total / args.steps
     value = 1000.0 / ms_step
-    st = stats.cpu().numpy().tolist()
+    st = stats.cpu().numpy().tolist() if stats is not None else [0] * 5
     rmax = float(torch.linalg.vector_norm(emb.Y.double(), dim=1).max())
     print("bench: BH %d steps %.3f ms/step (wall %.2fs) stats=%s rmax=%.6f"
           % (args.steps, ms_step, wall, st, rmax), file=sys.stderr, flush=True)
@@ -245,7 +246,9 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kt.items() if v[1]},
         "bh_counts_per_step": {"tests": st[0] // max(1, args.steps),
                                "accepted_cells": st[1] // max(1, args.steps),
-                               "leaf_pairs": st[2] // max(1, args.steps)},
+                               "leaf_pairs": st[2] // max(1, args.steps),
+                               "wave_node_visits": st[3] // max(1, args.steps),
+                               "wave_visits_with_work": st[4] // max(1, args.steps)},
         "setup_s": {"generate": round(gen_s, 2), "affinities_gpu": round(aff_s, 3)},
         "roofline": roof,
         "cpu_baseline": cpu,

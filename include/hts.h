@@ -148,8 +148,9 @@ hts_status hts_gradient_exact(hts_ctx ctx, hts_stream stream, const void *Y,
 /* Barnes-Hut repulsion (eq. (19)): a cell whose diameter r_cell and midpoint
  * m satisfy r_cell / d(y_i, m) < theta stands for its N_cell points;
  * theta = 0 evaluates every pair.  tree must have been built from the same Y.
- * stats_dev: NULL or device uint64[3] to which the call ADDS the number of
- * node tests, accepted cells and exact leaf pairs. */
+ * stats_dev: NULL or device uint64[5] to which the call ADDS the number of
+ * node tests, accepted cells and exact leaf pairs (per query), then the
+ * node visits and the visits with at least one interaction (per wave). */
 hts_status hts_gradient_bh(hts_ctx ctx, hts_stream stream, const void *Y,
                            int64_t n, int32_t dtype, const int64_t *row_ptr,
                            const int32_t *col_idx, const void *p_val,

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 
 #include "hts_impl.hpp"
 
@@ -176,6 +177,11 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
     t->max_depth = max_depth;
     t->cap_nodes = cap;
     t->nb = cdiv(n_max, kBlock);
+    int fd = 3;
+    if (const char *e = std::getenv("HTS_FRONTIER_DEPTH")) fd = std::atoi(e);  // tuning knob
+    if (fd < 1) fd = 1;
+    if (fd > 5) fd = 5;
+    t->fdepth = max_depth < fd ? max_depth : fd;
     size_t nm = (size_t)n_max;
     struct A { void **p; size_t bytes; } allocs[] = {
         {(void **)&t->r, nm * 8},
@@ -196,6 +202,8 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
         {(void **)&t->r_cell, (size_t)cap * 8},
         {(void **)&t->node_first, (size_t)cap * 4},
         {(void **)&t->sinhalf, 32 * 8},
+        {(void **)&t->parent, (size_t)cap * 4},
+        {(void **)&t->frontier, 1024 * 4},
     };
     hts_status s = HTS_OK;
     for (auto &a : allocs) {
@@ -234,7 +242,8 @@ hts_status hts_tree_destroy(hts_tree t) {
     hipDeviceSynchronize();
     void *ptrs[] = {t->r, t->phi, t->mm, t->root, t->keys_in, t->keys, t->idx_in, t->perm,
                     t->sort_tmp, t->ncnt_part, t->q_part, t->node_start, t->psum, t->d_m,
-                    t->spts, t->nodes, t->r_cell, t->node_first, t->sinhalf};
+                    t->spts, t->nodes, t->r_cell, t->node_first, t->sinhalf, t->parent,
+                    t->frontier};
     for (void *p : ptrs)
         if (p) hipFree(p);
     delete t;
@@ -364,16 +373,11 @@ static hts_status bh_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, cons
                           T *grad, double *z_dev, uint64_t *stats) {
     HTS_OKR(ensure(c->pts, (size_t)n * sizeof(PointRec<T>)));
     HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
-    HTS_OKR(ensure(c->frep, (size_t)n * 2 * sizeof(T)));
-    HTS_OKR(ensure(c->zpart, (size_t)(cdiv(n, kBlock) * (kBlock / kWave) + 8) * sizeof(double)));
     PointRec<T> *pts = (PointRec<T> *)c->pts.p;
     HTS_OKR(tree_thresholds(c, st, t, sizeof(T) == 8 ? HTS_F64 : HTS_F32, theta));
     HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
     HTS_OKR(launch_attract<T>(c, st, pts, rp, col, val, n, (T *)c->fattr.p));
-    int64_t nz = 0;
-    HTS_OKR(launch_traverse<T>(c, st, t, n, (T *)c->frep.p, (double *)c->zpart.p, &nz, stats));
-    return launch_finalize<T, T>(c, st, (const T *)c->fattr.p, (const T *)c->frep.p,
-                                 (const double *)c->zpart.p, nz, n, ex, grad, z_dev);
+    return launch_bh_repulsion<T>(c, st, t, n, (const T *)c->fattr.p, ex, grad, z_dev, stats);
 }
 
 extern "C" {

@@ -102,6 +102,9 @@ struct hts_tree_s {
     double *r_cell = nullptr;      // [cap_nodes]
     int32_t *node_first = nullptr; // [cap_nodes]
     double *sinhalf = nullptr;     // [32] sin(pi / 2^l), 1 for l <= 1
+    int32_t *parent = nullptr;     // [cap_nodes] parent node (-1 for the root)
+    int32_t *frontier = nullptr;   // [4^fdepth] node of each frontier cell, or -1
+    int32_t fdepth = 0;            // depth of the frontier cells that split the traversal
 };
 
 namespace hts {
@@ -149,9 +152,10 @@ template <typename T>
 hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, const int64_t *rp,
                           const int32_t *col, const T *val, int64_t n, T *fattr);
 
+// Barnes-Hut repulsion over the tree and the combine g = 4 (a F_attr - F_rep / Z)
 template <typename T>
-hts_status launch_traverse(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, T *frep,
-                           double *zpart, int64_t *nz_out, uint64_t *stats);
+hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, const T *fattr,
+                               double ex, T *grad, double *z_dev, uint64_t *stats);
 
 template <typename T>
 hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,

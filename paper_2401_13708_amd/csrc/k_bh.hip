@@ -1,68 +1,143 @@
 // k_bh.hip -- Barnes-Hut repulsion over the polar quadtree (eq. (19) and the
 // depth-first traversal of Sec. 4-B).
 //
-// One wave owns 64 consecutive points of the key order (so its queries are
-// spatial neighbours) and walks the union of their traversals in pre-order.
-// The node index is uniform across the wave, so every node record arrives
-// through scalar loads; each lane keeps its own criterion decision.  The set
-// of lanes that still need a subtree is a 64-bit mask per depth, held in two
-// VGPRs used as lane-indexed arrays (readlane with the depth, a lane select to write).
-// At an internal node a lane in the mask either accepts the cell
-// (r_cell / d(y_i, m) < theta, tested as t > cosh(r_cell/theta) - 1 with the
+// A query block is 64 consecutive points of the key order (spatial
+// neighbours), one per lane of a wave.  The block walks the tree depth-first;
+// the node index is uniform across the wave and each lane keeps its own
+// criterion decision: at an internal node a lane either accepts the cell
+// (r_cell / d(y_i, m) < theta, tested as t > cosh(r_cell / theta) - 1 with the
 // distance argument t in double) and adds N_cell w^2 d dd/dy, or joins the
-// mask of the children.  Leaves are evaluated exactly, skipping the query.
+// set of lanes that need the children.  Leaves are evaluated exactly, skipping
+// the query.  The lanes that need a subtree form a 64-bit mask per depth, kept
+// in two VGPRs used as lane-indexed arrays (readlane with the depth to read,
+// a lane select to write).  Node records are read from a window of 64
+// consecutive pre-order records held one per lane (one coalesced load, then
+// readlane), so a subtree of up to 64 nodes is walked without memory traffic.
+//
+// One wave walking the whole tree for its block is a long serial chain, so the
+// walk is split in two phases:
+//  A. one wave per query block walks the nodes that hold more than S points;
+//     when some lanes reject a smaller cell, the cell and their mask become a
+//     work item instead of being descended;
+//  B. persistent waves walk the work items, each a short independent chain.
+// Every item writes its own partial force per lane and partial Z; the combine
+// adds them in item order, so the result does not depend on scheduling.
+#include <cstdlib>
+
 #include "hts_impl.hpp"
 #include "hts_math.hpp"
 
 namespace hts {
 
-template <typename T, bool STATS>
-__global__ __launch_bounds__(kBlock) void k_traverse(const NodeRec<T> *__restrict__ nodes,
-                                                     const int32_t *__restrict__ d_m,
-                                                     const PointRec<T> *__restrict__ spts,
-                                                     const uint32_t *__restrict__ perm, int64_t n,
-                                                     T *__restrict__ frep,
-                                                     double *__restrict__ zpart,
-                                                     unsigned long long *__restrict__ stats) {
-    const int lane = (int)(threadIdx.x & (kWave - 1));
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = q < n;
-    const PointRec<T> me = spts[valid ? q : 0];
-    const int M = uniform(*d_m);
+constexpr int kStats = 5;
+constexpr int kItemCap = 256;  // items one query block can hand to phase B
 
-    T fx = 0, fy = 0;
-    double z = 0.0;
-    unsigned long long n_test = 0, n_acc = 0, n_pair = 0;
+struct Counters {
+    unsigned long long test = 0, acc = 0, pair = 0, step = 0, work = 0;
+};
 
-    uint64_t act = __ballot(valid);
-    int mlo = lane == 0 ? (int)(uint32_t)act : 0;
-    int mhi = lane == 0 ? (int)(uint32_t)(act >> 32) : 0;
+template <typename T>
+__device__ __forceinline__ void add_term(const PointRec<T> &me, T ox, T oy, double oib, double t,
+                                         double dd, T weight, T &fx, T &fy, double &z) {
+    PairTerm<T> r = pair_term<T>(me.x, me.y, me.ia, ox, oy, oib, t, dd);
+    T coef = weight * r.w * r.w * r.base;
+    fx += coef * r.vx;
+    fy += coef * r.vy;
+    z += (double)(weight * r.w);
+}
 
-    int k = 0;
-    while (k < M) {
-        const NodeRec<T> nd = nodes[k];
-        const uint32_t nxd = (uint32_t)uniform((int)nd.next_depth);
+// 64 consecutive node records, record wbase + r held by lane r
+template <typename T>
+struct Window {
+    uint4 v[sizeof(NodeRec<T>) / 16];
+};
+
+template <typename T>
+__device__ __forceinline__ void window_load(Window<T> &win, const NodeRec<T> *__restrict__ nodes,
+                                            int base, int M, int lane) {
+    int idx = base + lane;
+    if (idx >= M) idx = M - 1;
+    const uint4 *src = reinterpret_cast<const uint4 *>(nodes + idx);
+#pragma unroll
+    for (int j = 0; j < (int)(sizeof(NodeRec<T>) / 16); ++j) win.v[j] = src[j];
+}
+
+template <typename T>
+__device__ __forceinline__ NodeRec<T> window_get(const Window<T> &win, int r) {
+    uint32_t d[sizeof(NodeRec<T>) / 4];
+#pragma unroll
+    for (int j = 0; j < (int)(sizeof(NodeRec<T>) / 16); ++j) {
+        d[4 * j + 0] = (uint32_t)__builtin_amdgcn_readlane((int)win.v[j].x, r);
+        d[4 * j + 1] = (uint32_t)__builtin_amdgcn_readlane((int)win.v[j].y, r);
+        d[4 * j + 2] = (uint32_t)__builtin_amdgcn_readlane((int)win.v[j].z, r);
+        d[4 * j + 3] = (uint32_t)__builtin_amdgcn_readlane((int)win.v[j].w, r);
+    }
+    NodeRec<T> rec;
+    __builtin_memcpy(&rec, d, sizeof(rec));
+    return rec;
+}
+
+// Depth-first walk of the pre-order range [k, kend), which starts at a node
+// of depth d0 and holds its subtree, for the lanes in mask0.  With EMIT, an
+// internal node of at most S points that some lanes reject is appended to the
+// block's item list (while there is room) instead of being descended.
+template <typename T, bool STATS, bool EMIT, bool WIN>
+__device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M,
+                                     const PointRec<T> *__restrict__ spts, const PointRec<T> &me,
+                                     int64_t q, int lane, int k, int kend, int d0, uint64_t mask0,
+                                     int S, int *__restrict__ item_node,
+                                     uint64_t *__restrict__ item_mask, int &nitems, T &fx, T &fy,
+                                     double &z, Counters &c) {
+    int mlo = lane == d0 ? (int)(uint32_t)mask0 : 0;
+    int mhi = lane == d0 ? (int)(uint32_t)(mask0 >> 32) : 0;
+    int wbase = k;
+    Window<T> win;
+    if (WIN) window_load<T>(win, nodes, wbase, M, lane);
+    NodeRec<T> nrec;
+    if (!WIN) nrec = nodes[k < M ? k : M - 1];
+    while (k < kend) {
+        NodeRec<T> cur;
+        if (WIN) {
+            // small contiguous subtrees: records from the register window
+            if (k - wbase >= kWave) {
+                wbase = k;
+                window_load<T>(win, nodes, wbase, M, lane);
+            }
+            cur = window_get<T>(win, k - wbase);
+        } else {
+            // sparse walks near the root: scalar loads, which hit the scalar
+            // cache for the shared top levels; both possible successors are
+            // fetched while this node is evaluated
+            cur = nrec;
+        }
+        const uint32_t nxd = (uint32_t)uniform((int)cur.next_depth);
         const int next = (int)(nxd & kNextMask);
         const int depth = (int)(nxd >> kNextBits);
         const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
         const bool in = (m >> lane) & 1ull;
+        NodeRec<T> down, over;
+        if (!WIN) {
+            down = nodes[k + 1 < M ? k + 1 : k];
+            over = nodes[next < M ? next : k];
+        }
+        if (STATS) c.step += 1;
         if (next == k + 1) {
             // leaf: exact terms with each of its points, skipping the query
-            const int64_t first = (int64_t)__double_as_longlong(nd.c);
-            const int cnt = uniform(nd.count);
+            const int64_t first = (int64_t)__double_as_longlong(cur.c);
+            const int cnt = uniform(cur.count);
             if (cnt == 1) {
                 const bool use = in && first != q;
                 if (use) {
                     double dd;
-                    double t = dist_arg<T>(me.x, me.y, me.ia, nd.mx, nd.my, nd.ib, dd);
-                    PairTerm<T> r = pair_term<T>(me.x, me.y, me.ia, nd.mx, nd.my, nd.ib, t, dd);
-                    T coef = r.w * r.w * r.base;
-                    fx += coef * r.vx;
-                    fy += coef * r.vy;
-                    z += (double)r.w;
+                    double t = dist_arg<T>(me.x, me.y, me.ia, cur.mx, cur.my, cur.ib, dd);
+                    add_term<T>(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, z);
                 }
-                if (STATS) n_pair += __popcll(__ballot(use));
+                if (STATS) {
+                    const uint64_t um = __ballot(use);
+                    c.pair += __popcll(um);
+                    c.work += um != 0;
+                }
             } else {
                 for (int a = 0; a < cnt; ++a) {
                     const PointRec<T> o = spts[first + a];
@@ -70,83 +145,317 @@ __global__ __launch_bounds__(kBlock) void k_traverse(const NodeRec<T> *__restric
                     if (use) {
                         double dd;
                         double t = dist_arg<T>(me.x, me.y, me.ia, o.x, o.y, o.ia, dd);
-                        PairTerm<T> r = pair_term<T>(me.x, me.y, me.ia, o.x, o.y, o.ia, t, dd);
-                        T coef = r.w * r.w * r.base;
-                        fx += coef * r.vx;
-                        fy += coef * r.vy;
-                        z += (double)r.w;
+                        add_term<T>(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, z);
                     }
-                    if (STATS) n_pair += __popcll(__ballot(use));
+                    if (STATS) c.pair += __popcll(__ballot(use));
                 }
             }
             k = next;
+            if (!WIN) nrec = over;
         } else {
             bool acc = false;
             if (in) {
                 double dd;
-                double t = dist_arg<T>(me.x, me.y, me.ia, nd.mx, nd.my, nd.ib, dd);
-                acc = t > nd.c;
-                if (acc) {
-                    PairTerm<T> r = pair_term<T>(me.x, me.y, me.ia, nd.mx, nd.my, nd.ib, t, dd);
-                    T nc = (T)nd.count;
-                    T coef = nc * r.w * r.w * r.base;
-                    fx += coef * r.vx;
-                    fy += coef * r.vy;
-                    z += (double)(nc * r.w);
-                }
+                double t = dist_arg<T>(me.x, me.y, me.ia, cur.mx, cur.my, cur.ib, dd);
+                acc = t > cur.c;
+                if (acc) add_term<T>(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, z);
             }
             const uint64_t rej = __ballot(in && !acc);
             if (STATS) {
-                n_test += __popcll(m);
-                n_acc += __popcll(__ballot(acc));
+                const uint64_t am = __ballot(acc);
+                c.test += __popcll(m);
+                c.acc += __popcll(am);
+                c.work += am != 0;
             }
-            if (rej) {
+            if (EMIT && rej && cur.count <= S && nitems < kItemCap) {
+                if (lane == 0) {
+                    item_node[nitems] = k;
+                    item_mask[nitems] = rej;
+                }
+                ++nitems;
+                k = next;
+                if (!WIN) nrec = over;
+            } else if (rej) {
                 const bool here = lane == depth + 1;
                 mlo = here ? (int)(uint32_t)rej : mlo;
                 mhi = here ? (int)(uint32_t)(rej >> 32) : mhi;
                 k = k + 1;
+                if (!WIN) nrec = down;
             } else {
                 k = next;
+                if (!WIN) nrec = over;
             }
         }
     }
+}
+
+template <bool STATS>
+__device__ __forceinline__ void put_stats(uint32_t *__restrict__ sp, const Counters &c) {
+    if (!STATS) return;
+    sp[0] = (uint32_t)c.test;
+    sp[1] = (uint32_t)c.acc;
+    sp[2] = (uint32_t)c.pair;
+    sp[3] = (uint32_t)c.step;
+    sp[4] = (uint32_t)c.work;
+}
+
+// Phase A: one wave per query block over the nodes of more than S points.
+template <typename T, bool STATS>
+__global__ __launch_bounds__(kBlock) void k_bh_top(
+    const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
+    const PointRec<T> *__restrict__ spts, int64_t n, int64_t nqb, int S,
+    int *__restrict__ item_node, uint64_t *__restrict__ item_mask, int *__restrict__ nitems_out,
+    T *__restrict__ part0, double *__restrict__ ztop, uint32_t *__restrict__ stats_top,
+    unsigned *__restrict__ dense_count, int *__restrict__ dense) {
+    const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (qb >= nqb) return;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int64_t q = qb * kWave + lane;
+    const bool valid = q < n;
+    const PointRec<T> me = spts[valid ? q : 0];
+    const int M = uniform(*d_m);
+    T fx = 0, fy = 0;
+    double z = 0.0;
+    Counters c;
+    int nitems = 0;
+    walk<T, STATS, true, false>(nodes, M, spts, me, q, lane, 0, M, 0, __ballot(valid), S,
+                                item_node + qb * kItemCap, item_mask + qb * kItemCap, nitems, fx,
+                                fy, z, c);
+    // reserve a contiguous run of the dense item list (one atomic per block;
+    // the order of the runs does not matter, each item keeps its own slot)
+    int base = 0;
+    if (lane == 0 && nitems > 0) base = (int)atomicAdd(dense_count, (unsigned)nitems);
+    base = __shfl(base, 0, 64);
+    for (int j = lane; j < nitems; j += kWave) dense[base + j] = (int)(qb * kItemCap + j);
     if (valid) {
-        uint32_t o = perm[q];
-        frep[2 * (int64_t)o] = fx;
-        frep[2 * (int64_t)o + 1] = fy;
+        part0[2 * q] = fx;
+        part0[2 * q + 1] = fy;
     }
-    double zs = wave_sum(z);
+    const double zs = wave_sum(z);
     if (lane == 0) {
-        zpart[q / kWave] = zs;
-        if (STATS) {
-            atomicAdd(&stats[0], n_test);
-            atomicAdd(&stats[1], n_acc);
-            atomicAdd(&stats[2], n_pair);
+        ztop[qb] = zs;
+        nitems_out[qb] = nitems;
+        put_stats<STATS>(stats_top + qb * kStats, c);
+    }
+}
+
+// clears the dense-list counter (a kernel, not a memset, so the sequence can
+// be captured in a graph)
+__global__ void k_zero_u32(unsigned *p) {
+    if (threadIdx.x == 0) *p = 0u;
+}
+
+// Phase B: persistent waves over the dense item list; item g is slot j of
+// query block qb = g / kItemCap.
+template <typename T, bool STATS>
+__global__ __launch_bounds__(kBlock) void k_bh_items(
+    const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
+    const PointRec<T> *__restrict__ spts, int64_t n, int64_t nqb,
+    const int *__restrict__ item_node, const uint64_t *__restrict__ item_mask,
+    const unsigned *__restrict__ dense_count, const int *__restrict__ dense,
+    T *__restrict__ part, double *__restrict__ zitem, uint32_t *__restrict__ stats_items) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int M = uniform(*d_m);
+    const int64_t total = (int64_t)uniform((int)*dense_count);
+    const int64_t G = (int64_t)gridDim.x * (kBlock / kWave);
+    int dummy = 0;
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < total;
+         i += G) {
+        const int64_t g = uniform(dense[i]);
+        const int64_t qb = g / kItemCap;
+        const int64_t q = qb * kWave + lane;
+        const bool valid = q < n;
+        const PointRec<T> me = spts[valid ? q : 0];
+        const int f = uniform(item_node[g]);
+        const uint64_t mask = ((uint64_t)(uint32_t)uniform((int)(item_mask[g] >> 32)) << 32) |
+                              (uint64_t)(uint32_t)uniform((int)item_mask[g]);
+        const uint32_t fnd = (uint32_t)uniform((int)nodes[f].next_depth);
+        T fx = 0, fy = 0;
+        double z = 0.0;
+        Counters c;
+        // the item's lanes rejected node f in phase A: start at its children
+        walk<T, STATS, false, true>(nodes, M, spts, me, q, lane, f + 1, (int)(fnd & kNextMask),
+                              (int)(fnd >> kNextBits) + 1, mask, 0, nullptr, nullptr, dummy, fx, fy,
+                              z, c);
+        if (valid) {
+            T *o = part + (g * kWave + lane) * 2;
+            o[0] = fx;
+            o[1] = fy;
+        }
+        const double zs = wave_sum(z);
+        if (lane == 0) {
+            zitem[g] = zs;
+            put_stats<STATS>(stats_items + g * kStats, c);
         }
     }
 }
 
+// Combine, stage 1: one wave per query block adds its partials in item order;
+// the counters of the block are added to the caller's totals.
+template <typename T, bool STATS>
+__global__ __launch_bounds__(kBlock) void k_bh_gather(
+    const T *__restrict__ part0, const double *__restrict__ ztop, const T *__restrict__ part,
+    const double *__restrict__ zitem, const int *__restrict__ nitems_in, int64_t n, int64_t nqb,
+    T *__restrict__ frep, double *__restrict__ zq, const uint32_t *__restrict__ stats_top,
+    const uint32_t *__restrict__ stats_items, unsigned long long *__restrict__ stats) {
+    const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (qb >= nqb) return;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int64_t q = qb * kWave + lane;
+    const bool valid = q < n;
+    const int ni = uniform(nitems_in[qb]);
+    T fx = valid ? part0[2 * q] : (T)0, fy = valid ? part0[2 * q + 1] : (T)0;
+    for (int j = 0; j < ni; ++j) {
+        const T *p = part + ((qb * kItemCap + j) * kWave + lane) * 2;
+        if (valid) {
+            fx += p[0];
+            fy += p[1];
+        }
+    }
+    if (valid) {
+        frep[2 * q] = fx;
+        frep[2 * q + 1] = fy;
+    }
+    double zl = 0.0;
+    for (int j = lane; j < ni; j += kWave) zl += zitem[qb * kItemCap + j];
+    const double zs = wave_sum(zl);
+    if (lane == 0) zq[qb] = ztop[qb] + zs;
+    if (STATS) {
+        unsigned long long s[kStats];
+#pragma unroll
+        for (int a = 0; a < kStats; ++a) s[a] = 0;
+        for (int j = lane; j < ni; j += kWave)
+#pragma unroll
+            for (int a = 0; a < kStats; ++a) s[a] += stats_items[(qb * kItemCap + j) * kStats + a];
+#pragma unroll
+        for (int a = 0; a < kStats; ++a) {
+            unsigned long long v = s[a];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) atomicAdd(&stats[a], v + stats_top[qb * kStats + a]);
+        }
+    }
+}
+
+// Combine, stage 2: Z = sum of the block totals in block order (repeated by
+// every block), then g_i = 4 (a F_attr,i - F_rep,i / Z) scattered to input order.
 template <typename T>
-hts_status launch_traverse(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, T *frep,
-                           double *zpart, int64_t *nz_out, uint64_t *stats) {
-    TimedScope ts(ctx, st, HTS_K_TRAVERSE);
-    dim3 grid(cdiv(n, kBlock));
+__global__ __launch_bounds__(kBlock) void k_bh_finalize(
+    const T *__restrict__ fattr, const T *__restrict__ frep, const double *__restrict__ zq,
+    int64_t nqb, const uint32_t *__restrict__ perm, int64_t n, double ex, T *__restrict__ grad,
+    double *__restrict__ z_dev, uint32_t *__restrict__ err) {
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (int64_t a = threadIdx.x; a < nqb; a += kBlock) s += zq[a];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double Z = sh[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *z_dev = Z;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t i = perm[q];
+    const double inv = 1.0 / Z;
+    const double gx = 4.0 * (ex * (double)fattr[2 * (int64_t)i] - (double)frep[2 * q] * inv);
+    const double gy = 4.0 * (ex * (double)fattr[2 * (int64_t)i + 1] - (double)frep[2 * q + 1] * inv);
+    const T ox = (T)gx, oy = (T)gy;
+    if (!isfinite(ox) || !isfinite(oy)) atomicOr(err, HTS_ERR_NONFINITE_GRAD);
+    grad[2 * (int64_t)i] = ox;
+    grad[2 * (int64_t)i + 1] = oy;
+}
+
+static int item_points() {
+    static int s = [] {
+        int v = 256;
+        if (const char *e = std::getenv("HTS_ITEM_POINTS")) v = std::atoi(e);  // tuning knob
+        return v < 1 ? 1 : v;
+    }();
+    return s;
+}
+
+template <typename T>
+hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, const T *fattr,
+                               double ex, T *grad, double *z_dev, uint64_t *stats) {
+    const int64_t nqb = cdiv(n, kWave);
+    const int64_t slots = nqb * kItemCap;
+    const int S = item_points();
+    // workspace: item lists, partials, per-block sums
+    const size_t b_node = (size_t)slots * 4, b_mask = (size_t)slots * 8, b_nit = (size_t)nqb * 4;
+    const size_t b_part0 = (size_t)n * 2 * sizeof(T), b_ztop = (size_t)nqb * 8;
+    const size_t b_part = (size_t)slots * kWave * 2 * sizeof(T), b_zitem = (size_t)slots * 8;
+    const size_t b_frep = (size_t)nqb * kWave * 2 * sizeof(T), b_zq = (size_t)nqb * 8;
+    const size_t b_st = stats ? (size_t)(slots + nqb) * kStats * 4 : 0;
+    const size_t b_dense = (size_t)slots * 4 + 256;
+    size_t off[11], tot = 0;
+    const size_t sizes[11] = {b_node, b_mask, b_nit, b_part0, b_ztop, b_part,
+                              b_zitem, b_frep, b_zq, b_st, b_dense};
+    for (int a = 0; a < 11; ++a) {
+        off[a] = tot;
+        tot += (sizes[a] + 255) & ~(size_t)255;
+    }
+    HTS_OKR(ensure(ctx->part, tot));
+    char *base = (char *)ctx->part.p;
+    int *item_node = (int *)(base + off[0]);
+    uint64_t *item_mask = (uint64_t *)(base + off[1]);
+    int *nitems = (int *)(base + off[2]);
+    T *part0 = (T *)(base + off[3]);
+    double *ztop = (double *)(base + off[4]);
+    T *part = (T *)(base + off[5]);
+    double *zitem = (double *)(base + off[6]);
+    T *frep = (T *)(base + off[7]);
+    double *zq = (double *)(base + off[8]);
+    uint32_t *st_items = stats ? (uint32_t *)(base + off[9]) : nullptr;
+    uint32_t *st_top = stats ? st_items + (size_t)slots * kStats : nullptr;
+    unsigned *dense_count = (unsigned *)(base + off[10]);
+    int *dense = (int *)(base + off[10] + 256);
+
     const NodeRec<T> *nodes = (const NodeRec<T> *)t->nodes;
     const PointRec<T> *spts = (const PointRec<T> *)t->spts;
+    const dim3 gq(cdiv(nqb, kBlock / kWave));
+    int64_t gi = cdiv(slots, kBlock / kWave);
+    if (gi > 256 * 8) gi = 256 * 8;  // persistent: enough waves to fill the chip
+    {
+        TimedScope ts(ctx, st, HTS_K_TRAVERSE);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kWave), 0, st, dense_count);
+        if (stats) {
+            hipLaunchKernelGGL((k_bh_top<T, true>), gq, dim3(kBlock), 0, st, nodes, t->d_m, spts,
+                               n, nqb, S, item_node, item_mask, nitems, part0, ztop, st_top,
+                               dense_count, dense);
+            hipLaunchKernelGGL((k_bh_items<T, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
+                               spts, n, nqb, item_node, item_mask, dense_count, dense, part, zitem,
+                               st_items);
+        } else {
+            hipLaunchKernelGGL((k_bh_top<T, false>), gq, dim3(kBlock), 0, st, nodes, t->d_m, spts,
+                               n, nqb, S, item_node, item_mask, nitems, part0, ztop, nullptr,
+                               dense_count, dense);
+            hipLaunchKernelGGL((k_bh_items<T, false>), dim3(gi), dim3(kBlock), 0, st, nodes,
+                               t->d_m, spts, n, nqb, item_node, item_mask, dense_count, dense, part,
+                               zitem, nullptr);
+        }
+        HTS_HIP(hipGetLastError());
+    }
+    TimedScope ts(ctx, st, HTS_K_FINALIZE);
     if (stats)
-        hipLaunchKernelGGL((k_traverse<T, true>), grid, dim3(kBlock), 0, st, nodes, t->d_m, spts,
-                           t->perm, n, frep, zpart, (unsigned long long *)stats);
+        hipLaunchKernelGGL((k_bh_gather<T, true>), gq, dim3(kBlock), 0, st, part0, ztop, part,
+                           zitem, nitems, n, nqb, frep, zq, st_top, st_items,
+                           (unsigned long long *)stats);
     else
-        hipLaunchKernelGGL((k_traverse<T, false>), grid, dim3(kBlock), 0, st, nodes, t->d_m, spts,
-                           t->perm, n, frep, zpart, (unsigned long long *)nullptr);
+        hipLaunchKernelGGL((k_bh_gather<T, false>), gq, dim3(kBlock), 0, st, part0, ztop, part,
+                           zitem, nitems, n, nqb, frep, zq, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_bh_finalize<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,
+                       zq, nqb, t->perm, n, ex, grad, z_dev, ctx->d_err);
     HTS_HIP(hipGetLastError());
-    *nz_out = (int64_t)grid.x * (kBlock / kWave);
     return HTS_OK;
 }
 
-template hts_status launch_traverse<float>(hts_ctx, hipStream_t, hts_tree, int64_t, float *,
-                                           double *, int64_t *, uint64_t *);
-template hts_status launch_traverse<double>(hts_ctx, hipStream_t, hts_tree, int64_t, double *,
-                                            double *, int64_t *, uint64_t *);
+template hts_status launch_bh_repulsion<float>(hts_ctx, hipStream_t, hts_tree, int64_t,
+                                               const float *, double, float *, double *,
+                                               uint64_t *);
+template hts_status launch_bh_repulsion<double>(hts_ctx, hipStream_t, hts_tree, int64_t,
+                                                const double *, double, double *, double *,
+                                                uint64_t *);
 
 }  // namespace hts

@@ -189,8 +189,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt
                                                        int32_t *__restrict__ node_start,
                                                        DD3 *__restrict__ psum, int64_t n,
                                                        int32_t *__restrict__ d_m, int64_t cap,
-                                                       uint32_t *__restrict__ err) {
+                                                       uint32_t *__restrict__ err,
+                                                       int32_t *__restrict__ frontier, int nslots) {
     __shared__ int scnt[kBlock];
+    for (int a = threadIdx.x; a < nslots; a += kBlock) frontier[a] = -1;
     __shared__ DD3 sq[kBlock];
     int64_t per = cdiv(nb, kBlock);
     int64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
@@ -306,7 +308,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
                                                  NodeRec<T> *__restrict__ nodes,
                                                  double *__restrict__ r_cell,
                                                  int32_t *__restrict__ node_first,
-                                                 int64_t cap, uint32_t *__restrict__ err) {
+                                                 int64_t cap, uint32_t *__restrict__ err,
+                                                 int32_t *__restrict__ parent,
+                                                 int32_t *__restrict__ frontier, int F) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     NodeSpan sp = node_span(keys, i, n, L);
@@ -349,6 +353,30 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
         rec.c = leaf ? __longlong_as_double((long long)i) : 0.0;
         nodes[k] = rec;
         node_first[k] = (int32_t)i;
+        // parent: the previous node at this position, or the depth-(l-1) node
+        // starting at the first point of the enclosing cell
+        int32_t par = -1;
+        if (l > sp.s) {
+            par = k - 1;
+        } else if (l > 0) {
+            const int sh = 2 * (L - (l - 1));
+            const uint64_t pre = sh >= 64 ? 0 : (key >> sh);
+            int64_t lo2 = 0, hi2 = i;  // first j with the same depth-(l-1) prefix
+            while (lo2 < hi2) {
+                int64_t mid = lo2 + ((hi2 - lo2) >> 1);
+                uint64_t pm = sh >= 64 ? 0 : (keys[mid] >> sh);
+                if (pm < pre) lo2 = mid + 1; else hi2 = mid;
+            }
+            const int s0 = lo2 > 0 ? lcp_levels(keys[lo2 - 1], keys[lo2], L) + 1 : 0;
+            par = node_start[lo2] + (l - 1 - s0);
+        }
+        parent[k] = par;
+        // frontier cell: depth F, or a leaf above it; its slot is its key
+        // prefix padded to F levels
+        if (l == F || (l < F && leaf)) {
+            const uint64_t pre = key >> (2 * (L - l));
+            frontier[pre << (2 * (F - l))] = k;
+        }
         // radial bounds of the cell (same arithmetic as the keys)
         while (lev < l) {
             int rb = (int)((key >> (2 * (L - 1 - lev) + 1)) & 1u);
@@ -407,7 +435,8 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
                        (PointRec<T> *)t->spts, t->node_start, t->psum, t->ncnt_part, t->q_part);
     HTS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, st, t->ncnt_part, t->q_part, nb,
-                       t->node_start, t->psum, n, t->d_m, t->cap_nodes, ctx->d_err);
+                       t->node_start, t->psum, n, t->d_m, t->cap_nodes, ctx->d_err, t->frontier,
+                       1 << (2 * t->fdepth));
     HTS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, st, t->node_start, t->psum, n,
                        t->ncnt_part, t->q_part);
@@ -415,7 +444,7 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     hipLaunchKernelGGL(k_emit<T>, dim3(nb), dim3(kBlock), 0, st, t->keys, n, L,
                        (const PointRec<T> *)t->spts, t->node_start, t->psum, t->root, t->sinhalf,
                        (NodeRec<T> *)t->nodes, t->r_cell, t->node_first, t->cap_nodes,
-                       ctx->d_err);
+                       ctx->d_err, t->parent, t->frontier, t->fdepth);
     HTS_HIP(hipGetLastError());
     t->n = n;
     t->dtype = sizeof(T) == 8 ? HTS_F64 : HTS_F32;
