@@ -26,7 +26,7 @@ METRIC = "BH gradient iters/sec at N=70k θ=0.5 vs exact; jobs/sec + p50/p99 job
 HBM_PEAK_GBS = 8000.0
 # Non-packed FP32 / FP64 vector rate: 256 CU x 64 lanes x 2.4 GHz x 2 (FMA)
 VALU_PEAK_TFLOPS = 78.6
-# Algorithmic flops of the Barnes-Hut traversal (see DESIGN.md): a criterion
+# Algorithmic flops of the Barnes-Hut traversal: a criterion
 # test computes t = 2|y-m|^2 ia ib and compares (9 flops); an interaction
 # (accepted cell or leaf point) adds sinh d, d, w, the force factor, the
 # direction vector and the three accumulations (26 flops).
@@ -43,6 +43,7 @@ def _src_hash(files):
 
 
 KERNEL_SOURCES = {"traverse": ["k_bh.hip", "hts_math.hpp", "hts_impl.hpp"],
+                  "items": ["k_bh.hip", "hts_math.hpp", "hts_impl.hpp"],
                   "attract": ["k_grad.hip", "hts_math.hpp", "hts_impl.hpp"],
                   "tree": ["k_tree.hip", "hts_math.hpp", "hts_impl.hpp"]}
 
@@ -104,8 +105,8 @@ def main():
                     help="also run a plain device copy of this size (for PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d (WORLD_SIZE %s) is not "
-              "supported (the multi-GPU sharding is described in DESIGN.md, not built)"
+        print("bench.py: the library runs on one GPU; --gpus %d (WORLD_SIZE %s) is not "
+              "supported: sharding by query rows across GPUs is not implemented"
               % (args.gpus, os.environ.get("WORLD_SIZE", "1")), file=sys.stderr)
         sys.exit(2)
 
@@ -133,37 +134,56 @@ def main():
     del Xd
     print("bench: affinities nnz=%d in %.2fs" % (nnz, aff_s), file=sys.stderr, flush=True)
 
-    emb = Embedding(ctx, rp, col, val, torch.from_numpy(Y0).to(dev), theta=args.theta)
-    for _ in range(args.warmup):
-        emb.iterate()
-    torch.cuda.synchronize()
-    if ctx.check() != 0:
-        raise RuntimeError("device error word set during warm-up")
-    print("bench: warm-up %d iterations done" % args.warmup, file=sys.stderr, flush=True)
+    Y0d = torch.from_numpy(Y0).to(dev)
 
-    stats = None if args.no_stats else torch.zeros(5, dtype=torch.int64, device=dev)
-    ctx.timing(not args.no_kernel_events)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        emb.iterate(stats)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_total = e0.elapsed_time(e1)
-    kt = ctx.timing_read()
-    ctx.timing(False)
-    bits = ctx.check()
-    if bits:
-        raise RuntimeError("device error word 0x%x in the timed region" % bits)
+    def run_pass(events, stats):
+        """Warm-up + the timed iterations from the same start; the iteration
+        is deterministic, so every pass follows the same trajectory."""
+        emb = Embedding(ctx, rp, col, val, Y0d, theta=args.theta)
+        for _ in range(args.warmup):
+            emb.iterate()
+        torch.cuda.synchronize()
+        if ctx.check() != 0:
+            raise RuntimeError("device error word set during warm-up")
+        ctx.timing(events)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            emb.iterate(stats)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        kt = ctx.timing_read()
+        ctx.timing(False)
+        bits = ctx.check()
+        if bits:
+            raise RuntimeError("device error word 0x%x in the timed region" % bits)
+        return emb, e0.elapsed_time(e1), wall, kt
+
+    # pass 1: the headline, nothing but the iterations on the stream
+    emb, ms_total, wall, _ = run_pass(False, None)
     ms_step = ms_total / args.steps
     value = 1000.0 / ms_step
-    st = stats.cpu().numpy().tolist() if stats is not None else [0] * 5
     rmax = float(torch.linalg.vector_norm(emb.Y.double(), dim=1).max())
-    print("bench: BH %d steps %.3f ms/step (wall %.2fs) stats=%s rmax=%.6f"
-          % (args.steps, ms_step, wall, st, rmax), file=sys.stderr, flush=True)
+    print("bench: BH %d steps %.3f ms/step (wall %.2fs) rmax=%.6f"
+          % (args.steps, ms_step, wall, rmax), file=sys.stderr, flush=True)
+    # pass 2: per-kernel durations from HIP events around each launch
+    kt = {}
+    if not args.no_kernel_events:
+        e2, _, _, kt = run_pass(True, None)
+        e2.close()
+        print("bench: kernel events %s" % {k: round(v[0] / args.steps, 4) for k, v in kt.items() if v[1]},
+              file=sys.stderr, flush=True)
+    # pass 3: traversal counters (the kernels' counting variants)
+    st = [0] * 10
+    if not args.no_stats:
+        stats = torch.zeros(10, dtype=torch.int64, device=dev)
+        e3, _, _, _ = run_pass(False, stats)
+        e3.close()
+        st = stats.cpu().numpy().tolist()
+        print("bench: traversal counts %s" % st, file=sys.stderr, flush=True)
 
     # exact O(N^2) gradient + step at the same N, from the same state
     exact_ips = None
@@ -185,38 +205,44 @@ def main():
         print("bench: exact %.3f ms/step" % (1000.0 / exact_ips), file=sys.stderr, flush=True)
 
     if args.copy_calibration_mib > 0:
+        # one elementwise kernel that reads and writes exactly this many bytes
+        # (the scale for the HBM byte counters of a profiler run)
         m = args.copy_calibration_mib * (1 << 20) // 4
         a = torch.ones(m, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
 
     # roofline of the dominant kernel of the timed region
     launches = {k: v[1] for k, v in kt.items()}
     kms = {k: v[0] for k, v in kt.items()}
-    dom = max(("tree", "attract", "traverse", "finalize", "step"), key=lambda k: kms.get(k, 0.0))
+    names = {"tree": "tree build (6 kernels)", "attract": "k_attract", "traverse": "k_bh_top",
+             "items": "k_bh_items", "finalize": "k_bh_gather + k_bh_finalize", "step": "k_step"}
+    dom = max(names, key=lambda k: kms.get(k, 0.0))
     roof = None
     if launches.get(dom, 0) > 0:
         avg_s = kms[dom] / launches[dom] / 1000.0
-        if dom == "traverse":
-            flops = (st[0] * F_TEST + (st[1] + st[2]) * F_PAIR) / launches[dom]
+        if dom in ("traverse", "items"):
+            share = st[5:10] if dom == "items" else [a - b for a, b in zip(st[:5], st[5:10])]
+            flops = (share[0] * F_TEST + (share[1] + share[2]) * F_PAIR) / launches[dom]
             ach = flops / avg_s / 1e12
             roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),
-                    "traffic": _traffic("traverse"), "kernel": "k_traverse",
-                    "avg_launch_us": round(avg_s * 1e6, 2)}
+                    "traffic": _traffic(dom), "kernel": names[dom],
+                    "avg_launch_us": round(avg_s * 1e6, 2),
+                    "flops_per_launch": round(flops)}
         else:
             if dom == "attract":
                 byts = 8.0 * nnz + 8.0 * (n + 1) + 16.0 * n + 8.0 * n
-            else:  # tree build, finalize, step: bytes they must move
+            else:  # tree build, combine, step: bytes they must move
                 byts = {"tree": 8.0 * n + 16 * n + 2 * 5 * 12.0 * n + 16 * n + 48.0 * 2 * n,
                         "finalize": 24.0 * n, "step": 56.0 * n}[dom]
             ach = byts / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                     "traffic": _traffic(dom) if dom in KERNEL_SOURCES else None,
-                    "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2)}
+                    "kernel": names[dom], "avg_launch_us": round(avg_s * 1e6, 2)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -248,7 +274,9 @@ def main():
                                "accepted_cells": st[1] // max(1, args.steps),
                                "leaf_pairs": st[2] // max(1, args.steps),
                                "wave_node_visits": st[3] // max(1, args.steps),
-                               "wave_visits_with_work": st[4] // max(1, args.steps)},
+                               "wave_visits_with_work": st[4] // max(1, args.steps),
+                               "share_of_item_walks": [round(b / a, 3) if a else 0.0
+                                                       for a, b in zip(st[:5], st[5:10])]},
         "setup_s": {"generate": round(gen_s, 2), "affinities_gpu": round(aff_s, 3)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -148,9 +148,12 @@ hts_status hts_gradient_exact(hts_ctx ctx, hts_stream stream, const void *Y,
 /* Barnes-Hut repulsion (eq. (19)): a cell whose diameter r_cell and midpoint
  * m satisfy r_cell / d(y_i, m) < theta stands for its N_cell points;
  * theta = 0 evaluates every pair.  tree must have been built from the same Y.
- * stats_dev: NULL or device uint64[5] to which the call ADDS the number of
- * node tests, accepted cells and exact leaf pairs (per query), then the
- * node visits and the visits with at least one interaction (per wave). */
+ * stats_dev: NULL or device uint64[10] to which the call ADDS, in [0..4],
+ * the number of node tests, accepted cells and exact leaf pairs (per query),
+ * then the node visits and the visits with at least one interaction (per
+ * wave); [5..9] receive the same five counts restricted to the second
+ * traversal kernel (the walks of the small subtrees), so the first kernel's
+ * share is the difference. */
 hts_status hts_gradient_bh(hts_ctx ctx, hts_stream stream, const void *Y,
                            int64_t n, int32_t dtype, const int64_t *row_ptr,
                            const int32_t *col_idx, const void *p_val,
@@ -183,12 +186,13 @@ hts_status hts_step(hts_ctx ctx, hts_stream stream, void *Y, void *update,
 enum {
     HTS_K_TREE = 0,      /* whole tree build */
     HTS_K_ATTRACT = 1,   /* attractive CSR kernel */
-    HTS_K_TRAVERSE = 2,  /* Barnes-Hut traversal kernel */
+    HTS_K_TRAVERSE = 2,  /* Barnes-Hut traversal, walk of the large cells */
     HTS_K_EXACT = 3,     /* exact repulsion kernel */
     HTS_K_FINALIZE = 4,  /* Z reduction and combine */
     HTS_K_STEP = 5,      /* Riemannian step */
     HTS_K_KNN = 6,       /* exact k-NN */
-    HTS_KCLASS_COUNT = 7
+    HTS_K_ITEMS = 7,     /* Barnes-Hut traversal, walks of the small subtrees */
+    HTS_KCLASS_COUNT = 8
 };
 hts_status hts_timing_enable(hts_ctx ctx, int32_t on);
 hts_status hts_timing_read(hts_ctx ctx, double *ms_out, int64_t *launches_out);

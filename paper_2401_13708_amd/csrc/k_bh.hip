@@ -332,7 +332,10 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
             unsigned long long v = s[a];
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) atomicAdd(&stats[a], v + stats_top[qb * kStats + a]);
+            if (lane == 0) {
+                atomicAdd(&stats[a], v + stats_top[qb * kStats + a]);
+                atomicAdd(&stats[kStats + a], v);
+            }
         }
     }
 }
@@ -369,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_finalize(
 
 static int item_points() {
     static int s = [] {
-        int v = 256;
+        int v = 512;
         if (const char *e = std::getenv("HTS_ITEM_POINTS")) v = std::atoi(e);  // tuning knob
         return v < 1 ? 1 : v;
     }();
@@ -417,26 +420,30 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const dim3 gq(cdiv(nqb, kBlock / kWave));
     int64_t gi = cdiv(slots, kBlock / kWave);
     if (gi > 256 * 8) gi = 256 * 8;  // persistent: enough waves to fill the chip
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kWave), 0, st, dense_count);
     {
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kWave), 0, st, dense_count);
-        if (stats) {
+        if (stats)
             hipLaunchKernelGGL((k_bh_top<T, true>), gq, dim3(kBlock), 0, st, nodes, t->d_m, spts,
                                n, nqb, S, item_node, item_mask, nitems, part0, ztop, st_top,
                                dense_count, dense);
-            hipLaunchKernelGGL((k_bh_items<T, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
-                               spts, n, nqb, item_node, item_mask, dense_count, dense, part, zitem,
-                               st_items);
-        } else {
+        else
             hipLaunchKernelGGL((k_bh_top<T, false>), gq, dim3(kBlock), 0, st, nodes, t->d_m, spts,
                                n, nqb, S, item_node, item_mask, nitems, part0, ztop, nullptr,
                                dense_count, dense);
+    }
+    {
+        TimedScope ts(ctx, st, HTS_K_ITEMS);
+        if (stats)
+            hipLaunchKernelGGL((k_bh_items<T, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
+                               spts, n, nqb, item_node, item_mask, dense_count, dense, part, zitem,
+                               st_items);
+        else
             hipLaunchKernelGGL((k_bh_items<T, false>), dim3(gi), dim3(kBlock), 0, st, nodes,
                                t->d_m, spts, n, nqb, item_node, item_mask, dense_count, dense, part,
                                zitem, nullptr);
-        }
-        HTS_HIP(hipGetLastError());
     }
+    HTS_HIP(hipGetLastError());
     TimedScope ts(ctx, st, HTS_K_FINALIZE);
     if (stats)
         hipLaunchKernelGGL((k_bh_gather<T, true>), gq, dim3(kBlock), 0, st, part0, ztop, part,

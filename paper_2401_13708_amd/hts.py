@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "hts.h")
 HTS_F32, HTS_F64 = 0, 1
 STATUS = {0: "HTS_OK", -1: "HTS_EINVAL", -2: "HTS_ENOMEM", -3: "HTS_EDEVICE",
           -4: "HTS_ECAPACITY", -5: "HTS_ENUMERIC"}
-KCLASS = ["tree", "attract", "traverse", "exact", "finalize", "step", "knn"]
+KCLASS = ["tree", "attract", "traverse", "exact", "finalize", "step", "knn", "items"]
 
 
 class HTSError(RuntimeError):
@@ -142,8 +142,8 @@ class Context:
         _ck(lib().hts_timing_enable(self.h, 1 if on else 0))
 
     def timing_read(self) -> dict:
-        ms = (C.c_double * 7)()
-        cnt = (C.c_int64 * 7)()
+        ms = (C.c_double * len(KCLASS))()
+        cnt = (C.c_int64 * len(KCLASS))()
         _ck(lib().hts_timing_read(self.h, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KCLASS)}
 
@@ -243,6 +243,8 @@ def gradient_bh(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, theta: flo
     z = torch.empty(1, dtype=torch.float64, device=Y.device) if z is None else z
     if stats is not None:
         _dev(stats, "stats", torch.int64)
+        if stats.numel() < 10:
+            raise ValueError("stats needs 10 int64 entries")
     _ck(lib().hts_gradient_bh(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
                               _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), float(exaggeration),
                               tree.h, float(theta), _ptr(grad), _ptr(z), _ptr(stats)))

@@ -32,7 +32,7 @@ def _run_bh(ctx, Y, rp, col, val, ex, theta, max_depth=20, stats=False):
     Yd = _dev(Y)
     tree = hts.Tree(ctx, Y.shape[0], max_depth)
     hts.build_polar_tree(ctx, Yd, tree)
-    st = torch.zeros(5, dtype=torch.int64, device="cuda") if stats else None
+    st = torch.zeros(10, dtype=torch.int64, device="cuda") if stats else None
     g, z = hts.gradient_bh(ctx, Yd, _dev(rp), _dev(col), _dev(val), tree, theta, ex, stats=st)
     torch.cuda.synchronize()
     assert ctx.check() == 0
@@ -101,6 +101,8 @@ def test_bh_f64_matches_oracle_bh(ctx, stage):
     t = oracle.Tree(Y)
     go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 1.0)
     assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    # the share of the second traversal kernel is part of the totals
+    assert all(0 <= b <= a for a, b in zip(st[:5], st[5:]))
     assert rel(g, go) < 1e-10
     # an accepted cell's midpoint carries the rounding of its sums, amplified
     # by 1 / (1 - |m|^2) near the rim
