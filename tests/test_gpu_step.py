@@ -30,7 +30,10 @@ def _sensitivity(Y, U, G, grad, eta, mu, mp, rel):
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("metric_power", [2, 1])
 def test_step_matches_oracle(ctx, stage, dtype, metric_power):
-    n = 3001
+    step_case(ctx, 3001, stage, dtype, metric_power)
+
+
+def step_case(ctx, n, stage, dtype, metric_power):
     g = synth.rng(3)
     Y = embedding(n, stage, dtype)
     U = (g.normal(size=(n, 2)) * 1e-3).astype(dtype)
