@@ -19,9 +19,14 @@
 //  A. one wave per query block walks the nodes that hold more than S points;
 //     when some lanes reject a smaller cell, the cell and their mask become a
 //     work item instead of being descended;
-//  B. persistent waves walk the work items, each a short independent chain.
-// Every item writes its own partial force per lane and partial Z; the combine
-// adds them in item order, so the result does not depend on scheduling.
+//  B. persistent waves walk the work items, each a short independent chain;
+//     an item record is self-contained (subtree, lane mask, query block), and
+//     a wave fetches the query points and first node window of its next item
+//     while it walks the current one.
+// Every item writes its own partial force per lane and partial Z; the items
+// of a query block occupy one contiguous run of the item list, and the
+// combine adds them in emission order, so the result does not depend on
+// scheduling.
 #include <cstdlib>
 
 #include "hts_impl.hpp"
@@ -31,6 +36,22 @@ namespace hts {
 
 constexpr int kStats = 5;
 constexpr int kItemCap = 256;  // items one query block can hand to phase B
+
+// work item as phase A records it (in LDS) ...
+struct LdsItem {
+    int32_t node;      // pre-order index of the rejected cell
+    uint32_t nd;       // its next | depth word
+    uint64_t mask;     // lanes that rejected it
+};
+// ... and as phase B reads it (one 32-byte scalar load)
+struct alignas(16) ItemRec {
+    int32_t node;
+    uint32_t nd;
+    int32_t qb;        // query block
+    int32_t pad0;
+    uint64_t mask;
+    uint64_t pad1;
+};
 
 struct Counters {
     unsigned long long test = 0, acc = 0, pair = 0, step = 0, work = 0;
@@ -81,18 +102,16 @@ __device__ __forceinline__ NodeRec<T> window_get(const Window<T> &win, int r) {
 // of depth d0 and holds its subtree, for the lanes in mask0.  With EMIT, an
 // internal node of at most S points that some lanes reject is appended to the
 // block's item list (while there is room) instead of being descended.
+// In WIN mode, win holds the records from k on.
 template <typename T, bool STATS, bool EMIT, bool WIN>
 __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M,
                                      const PointRec<T> *__restrict__ spts, const PointRec<T> &me,
                                      int64_t q, int lane, int k, int kend, int d0, uint64_t mask0,
-                                     int S, int *__restrict__ item_node,
-                                     uint64_t *__restrict__ item_mask, int &nitems, T &fx, T &fy,
-                                     double &z, Counters &c) {
+                                     int S, LdsItem *items, int &nitems, Window<T> win, T &fx,
+                                     T &fy, double &z, Counters &c) {
     int mlo = lane == d0 ? (int)(uint32_t)mask0 : 0;
     int mhi = lane == d0 ? (int)(uint32_t)(mask0 >> 32) : 0;
     int wbase = k;
-    Window<T> win;
-    if (WIN) window_load<T>(win, nodes, wbase, M, lane);
     NodeRec<T> nrec;
     if (!WIN) nrec = nodes[k < M ? k : M - 1];
     while (k < kend) {
@@ -168,10 +187,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 c.work += am != 0;
             }
             if (EMIT && rej && cur.count <= S && nitems < kItemCap) {
-                if (lane == 0) {
-                    item_node[nitems] = k;
-                    item_mask[nitems] = rej;
-                }
+                if (lane == 0) items[nitems] = LdsItem{k, nxd, rej};
                 ++nitems;
                 k = next;
                 if (!WIN) nrec = over;
@@ -204,12 +220,14 @@ template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_top(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
     const PointRec<T> *__restrict__ spts, int64_t n, int64_t nqb, int S,
-    int *__restrict__ item_node, uint64_t *__restrict__ item_mask, int *__restrict__ nitems_out,
-    T *__restrict__ part0, double *__restrict__ ztop, uint32_t *__restrict__ stats_top,
-    unsigned *__restrict__ dense_count, int *__restrict__ dense) {
+    int *__restrict__ item_base, int *__restrict__ nitems_out, T *__restrict__ part0,
+    double *__restrict__ ztop, uint32_t *__restrict__ stats_top, unsigned *__restrict__ dense_count,
+    ItemRec *__restrict__ dense) {
+    __shared__ LdsItem s_items[kBlock / kWave][kItemCap];
     const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (qb >= nqb) return;
     const int lane = (int)(threadIdx.x & (kWave - 1));
+    LdsItem *items = s_items[threadIdx.x / kWave];
     const int64_t q = qb * kWave + lane;
     const bool valid = q < n;
     const PointRec<T> me = spts[valid ? q : 0];
@@ -218,15 +236,20 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     double z = 0.0;
     Counters c;
     int nitems = 0;
-    walk<T, STATS, true, false>(nodes, M, spts, me, q, lane, 0, M, 0, __ballot(valid), S,
-                                item_node + qb * kItemCap, item_mask + qb * kItemCap, nitems, fx,
-                                fy, z, c);
-    // reserve a contiguous run of the dense item list (one atomic per block;
-    // the order of the runs does not matter, each item keeps its own slot)
+    walk<T, STATS, true, false>(nodes, M, spts, me, q, lane, 0, M, 0, __ballot(valid), S, items,
+                                nitems, Window<T>{}, fx, fy, z, c);
+    // reserve a contiguous run of the item list (one atomic per block; the
+    // runs of different blocks may come in any order)
     int base = 0;
     if (lane == 0 && nitems > 0) base = (int)atomicAdd(dense_count, (unsigned)nitems);
     base = __shfl(base, 0, 64);
-    for (int j = lane; j < nitems; j += kWave) dense[base + j] = (int)(qb * kItemCap + j);
+    // the records were written to LDS by lane 0 of this wave
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < nitems; j += kWave) {
+        const LdsItem it = items[j];
+        dense[base + j] = ItemRec{it.node, it.nd, (int32_t)qb, 0, it.mask, 0};
+    }
     if (valid) {
         part0[2 * q] = fx;
         part0[2 * q + 1] = fy;
@@ -234,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     const double zs = wave_sum(z);
     if (lane == 0) {
         ztop[qb] = zs;
+        item_base[qb] = base;
         nitems_out[qb] = nitems;
         put_stats<STATS>(stats_top + qb * kStats, c);
     }
@@ -245,79 +269,130 @@ __global__ void k_zero_u32(unsigned *p) {
     if (threadIdx.x == 0) *p = 0u;
 }
 
-// Phase B: persistent waves over the dense item list; item g is slot j of
-// query block qb = g / kItemCap.
+// one item record in scalar registers
+__device__ __forceinline__ ItemRec load_item(const ItemRec *__restrict__ dense, int64_t i) {
+    const ItemRec r = dense[i];
+    ItemRec u;
+    u.node = uniform(r.node);
+    u.nd = (uint32_t)uniform((int)r.nd);
+    u.qb = uniform(r.qb);
+    u.pad0 = 0;
+    u.mask = ((uint64_t)(uint32_t)uniform((int)(r.mask >> 32)) << 32) |
+             (uint64_t)(uint32_t)uniform((int)r.mask);
+    u.pad1 = 0;
+    return u;
+}
+
+// Phase B: persistent waves over the item list.  Item i is walked by wave
+// i mod G; while it is walked, the wave already holds the record of item
+// i + G and has the query points and first node window of that item in
+// flight, and the record of item i + 2G is being fetched.
 template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_items(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
-    const PointRec<T> *__restrict__ spts, int64_t n, int64_t nqb,
-    const int *__restrict__ item_node, const uint64_t *__restrict__ item_mask,
-    const unsigned *__restrict__ dense_count, const int *__restrict__ dense,
-    T *__restrict__ part, double *__restrict__ zitem, uint32_t *__restrict__ stats_items) {
+    const PointRec<T> *__restrict__ spts, int64_t n, const unsigned *__restrict__ dense_count,
+    const ItemRec *__restrict__ dense, T *__restrict__ part, double *__restrict__ zitem,
+    uint32_t *__restrict__ stats_items) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int M = uniform(*d_m);
     const int64_t total = (int64_t)uniform((int)*dense_count);
     const int64_t G = (int64_t)gridDim.x * (kBlock / kWave);
+    int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (i >= total) return;
     int dummy = 0;
-    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < total;
-         i += G) {
-        const int64_t g = uniform(dense[i]);
-        const int64_t qb = g / kItemCap;
-        const int64_t q = qb * kWave + lane;
+    ItemRec rec = load_item(dense, i);
+    int64_t q = (int64_t)rec.qb * kWave + lane;
+    PointRec<T> me = spts[q < n ? q : n - 1];
+    Window<T> win;
+    window_load<T>(win, nodes, rec.node + 1, M, lane);
+    ItemRec nrec = rec;
+    if (i + G < total) nrec = load_item(dense, i + G);
+    for (;;) {
+        const int64_t i1 = i + G, i2 = i + 2 * G;
+        // next item: query points and first window (its record is here)
+        PointRec<T> nme = me;
+        Window<T> nwin = win;
+        if (i1 < total) {
+            const int64_t nq = (int64_t)nrec.qb * kWave + lane;
+            nme = spts[nq < n ? nq : n - 1];
+            window_load<T>(nwin, nodes, nrec.node + 1, M, lane);
+        }
+        ItemRec nnrec = nrec;
+        if (i2 < total) nnrec = load_item(dense, i2);
+
         const bool valid = q < n;
-        const PointRec<T> me = spts[valid ? q : 0];
-        const int f = uniform(item_node[g]);
-        const uint64_t mask = ((uint64_t)(uint32_t)uniform((int)(item_mask[g] >> 32)) << 32) |
-                              (uint64_t)(uint32_t)uniform((int)item_mask[g]);
-        const uint32_t fnd = (uint32_t)uniform((int)nodes[f].next_depth);
         T fx = 0, fy = 0;
         double z = 0.0;
         Counters c;
-        // the item's lanes rejected node f in phase A: start at its children
-        walk<T, STATS, false, true>(nodes, M, spts, me, q, lane, f + 1, (int)(fnd & kNextMask),
-                              (int)(fnd >> kNextBits) + 1, mask, 0, nullptr, nullptr, dummy, fx, fy,
-                              z, c);
+        // the item's lanes rejected its node in phase A: start at its children
+        walk<T, STATS, false, true>(nodes, M, spts, me, q, lane, rec.node + 1,
+                                    (int)(rec.nd & kNextMask), (int)(rec.nd >> kNextBits) + 1,
+                                    rec.mask, 0, nullptr, dummy, win, fx, fy, z, c);
         if (valid) {
-            T *o = part + (g * kWave + lane) * 2;
+            T *o = part + (i * kWave + lane) * 2;
             o[0] = fx;
             o[1] = fy;
         }
         const double zs = wave_sum(z);
         if (lane == 0) {
-            zitem[g] = zs;
-            put_stats<STATS>(stats_items + g * kStats, c);
+            zitem[i] = zs;
+            put_stats<STATS>(stats_items + i * kStats, c);
         }
+        if (i1 >= total) break;
+        i = i1;
+        rec = nrec;
+        nrec = nnrec;
+        q = (int64_t)rec.qb * kWave + lane;
+        me = nme;
+        win = nwin;
     }
 }
 
-// Combine, stage 1: one wave per query block adds its partials in item order;
-// the counters of the block are added to the caller's totals.
+// Combine, stage 1: one wave per query block adds its partials in item order
+// (eight loads in flight at a time); the counters of the block are added to
+// the caller's totals.
 template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_gather(
     const T *__restrict__ part0, const double *__restrict__ ztop, const T *__restrict__ part,
-    const double *__restrict__ zitem, const int *__restrict__ nitems_in, int64_t n, int64_t nqb,
-    T *__restrict__ frep, double *__restrict__ zq, const uint32_t *__restrict__ stats_top,
+    const double *__restrict__ zitem, const int *__restrict__ item_base,
+    const int *__restrict__ nitems_in, int64_t n, int64_t nqb, T *__restrict__ frep,
+    double *__restrict__ zq, const uint32_t *__restrict__ stats_top,
     const uint32_t *__restrict__ stats_items, unsigned long long *__restrict__ stats) {
     const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (qb >= nqb) return;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int64_t q = qb * kWave + lane;
     const bool valid = q < n;
+    const int64_t b0 = uniform(item_base[qb]);
     const int ni = uniform(nitems_in[qb]);
     T fx = valid ? part0[2 * q] : (T)0, fy = valid ? part0[2 * q + 1] : (T)0;
-    for (int j = 0; j < ni; ++j) {
-        const T *p = part + ((qb * kItemCap + j) * kWave + lane) * 2;
-        if (valid) {
+    if (valid) {
+        constexpr int U = 8;
+        int j = 0;
+        for (; j + U <= ni; j += U) {
+            T px[U], py[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const T *p = part + ((b0 + j + u) * kWave + lane) * 2;
+                px[u] = p[0];
+                py[u] = p[1];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                fx += px[u];
+                fy += py[u];
+            }
+        }
+        for (; j < ni; ++j) {
+            const T *p = part + ((b0 + j) * kWave + lane) * 2;
             fx += p[0];
             fy += p[1];
         }
-    }
-    if (valid) {
         frep[2 * q] = fx;
         frep[2 * q + 1] = fy;
     }
     double zl = 0.0;
-    for (int j = lane; j < ni; j += kWave) zl += zitem[qb * kItemCap + j];
+    for (int j = lane; j < ni; j += kWave) zl += zitem[b0 + j];
     const double zs = wave_sum(zl);
     if (lane == 0) zq[qb] = ztop[qb] + zs;
     if (STATS) {
@@ -326,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
         for (int a = 0; a < kStats; ++a) s[a] = 0;
         for (int j = lane; j < ni; j += kWave)
 #pragma unroll
-            for (int a = 0; a < kStats; ++a) s[a] += stats_items[(qb * kItemCap + j) * kStats + a];
+            for (int a = 0; a < kStats; ++a) s[a] += stats_items[(b0 + j) * kStats + a];
 #pragma unroll
         for (int a = 0; a < kStats; ++a) {
             unsigned long long v = s[a];
@@ -385,35 +460,35 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const int64_t nqb = cdiv(n, kWave);
     const int64_t slots = nqb * kItemCap;
     const int S = item_points();
-    // workspace: item lists, partials, per-block sums
-    const size_t b_node = (size_t)slots * 4, b_mask = (size_t)slots * 8, b_nit = (size_t)nqb * 4;
+    // workspace: item list, partials, per-block sums
+    const size_t b_base = (size_t)nqb * 4, b_nit = (size_t)nqb * 4;
     const size_t b_part0 = (size_t)n * 2 * sizeof(T), b_ztop = (size_t)nqb * 8;
     const size_t b_part = (size_t)slots * kWave * 2 * sizeof(T), b_zitem = (size_t)slots * 8;
     const size_t b_frep = (size_t)nqb * kWave * 2 * sizeof(T), b_zq = (size_t)nqb * 8;
     const size_t b_st = stats ? (size_t)(slots + nqb) * kStats * 4 : 0;
-    const size_t b_dense = (size_t)slots * 4 + 256;
-    size_t off[11], tot = 0;
-    const size_t sizes[11] = {b_node, b_mask, b_nit, b_part0, b_ztop, b_part,
-                              b_zitem, b_frep, b_zq, b_st, b_dense};
-    for (int a = 0; a < 11; ++a) {
+    const size_t b_cnt = 256, b_dense = (size_t)slots * sizeof(ItemRec);
+    constexpr int R = 11;
+    size_t off[R], tot = 0;
+    const size_t sizes[R] = {b_base, b_nit, b_part0, b_ztop, b_part, b_zitem,
+                             b_frep, b_zq, b_st, b_cnt, b_dense};
+    for (int a = 0; a < R; ++a) {
         off[a] = tot;
         tot += (sizes[a] + 255) & ~(size_t)255;
     }
     HTS_OKR(ensure(ctx->part, tot));
     char *base = (char *)ctx->part.p;
-    int *item_node = (int *)(base + off[0]);
-    uint64_t *item_mask = (uint64_t *)(base + off[1]);
-    int *nitems = (int *)(base + off[2]);
-    T *part0 = (T *)(base + off[3]);
-    double *ztop = (double *)(base + off[4]);
-    T *part = (T *)(base + off[5]);
-    double *zitem = (double *)(base + off[6]);
-    T *frep = (T *)(base + off[7]);
-    double *zq = (double *)(base + off[8]);
-    uint32_t *st_items = stats ? (uint32_t *)(base + off[9]) : nullptr;
+    int *item_base = (int *)(base + off[0]);
+    int *nitems = (int *)(base + off[1]);
+    T *part0 = (T *)(base + off[2]);
+    double *ztop = (double *)(base + off[3]);
+    T *part = (T *)(base + off[4]);
+    double *zitem = (double *)(base + off[5]);
+    T *frep = (T *)(base + off[6]);
+    double *zq = (double *)(base + off[7]);
+    uint32_t *st_items = stats ? (uint32_t *)(base + off[8]) : nullptr;
     uint32_t *st_top = stats ? st_items + (size_t)slots * kStats : nullptr;
-    unsigned *dense_count = (unsigned *)(base + off[10]);
-    int *dense = (int *)(base + off[10] + 256);
+    unsigned *dense_count = (unsigned *)(base + off[9]);
+    ItemRec *dense = (ItemRec *)(base + off[10]);
 
     const NodeRec<T> *nodes = (const NodeRec<T> *)t->nodes;
     const PointRec<T> *spts = (const PointRec<T> *)t->spts;
@@ -425,33 +500,31 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
         if (stats)
             hipLaunchKernelGGL((k_bh_top<T, true>), gq, dim3(kBlock), 0, st, nodes, t->d_m, spts,
-                               n, nqb, S, item_node, item_mask, nitems, part0, ztop, st_top,
-                               dense_count, dense);
+                               n, nqb, S, item_base, nitems, part0, ztop, st_top, dense_count,
+                               dense);
         else
             hipLaunchKernelGGL((k_bh_top<T, false>), gq, dim3(kBlock), 0, st, nodes, t->d_m, spts,
-                               n, nqb, S, item_node, item_mask, nitems, part0, ztop, nullptr,
-                               dense_count, dense);
+                               n, nqb, S, item_base, nitems, part0, ztop, nullptr, dense_count,
+                               dense);
     }
     {
         TimedScope ts(ctx, st, HTS_K_ITEMS);
         if (stats)
             hipLaunchKernelGGL((k_bh_items<T, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
-                               spts, n, nqb, item_node, item_mask, dense_count, dense, part, zitem,
-                               st_items);
+                               spts, n, dense_count, dense, part, zitem, st_items);
         else
             hipLaunchKernelGGL((k_bh_items<T, false>), dim3(gi), dim3(kBlock), 0, st, nodes,
-                               t->d_m, spts, n, nqb, item_node, item_mask, dense_count, dense, part,
-                               zitem, nullptr);
+                               t->d_m, spts, n, dense_count, dense, part, zitem, nullptr);
     }
     HTS_HIP(hipGetLastError());
     TimedScope ts(ctx, st, HTS_K_FINALIZE);
     if (stats)
         hipLaunchKernelGGL((k_bh_gather<T, true>), gq, dim3(kBlock), 0, st, part0, ztop, part,
-                           zitem, nitems, n, nqb, frep, zq, st_top, st_items,
+                           zitem, item_base, nitems, n, nqb, frep, zq, st_top, st_items,
                            (unsigned long long *)stats);
     else
         hipLaunchKernelGGL((k_bh_gather<T, false>), gq, dim3(kBlock), 0, st, part0, ztop, part,
-                           zitem, nitems, n, nqb, frep, zq, nullptr, nullptr, nullptr);
+                           zitem, item_base, nitems, n, nqb, frep, zq, nullptr, nullptr, nullptr);
     hipLaunchKernelGGL(k_bh_finalize<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,
                        zq, nqb, t->perm, n, ex, grad, z_dev, ctx->d_err);
     HTS_HIP(hipGetLastError());
