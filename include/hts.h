@@ -111,8 +111,20 @@ hts_status hts_tree_create(hts_ctx ctx, int64_t n_max, int32_t max_depth,
                            hts_tree *out);
 hts_status hts_tree_destroy(hts_tree tree);
 
-/* Builds the tree of Y (n points, 2 <= n <= n_max) on the stream.  The tree
- * keeps its own copy of everything it needs; Y may change afterwards. */
+/* sync.  Job layout: the tree will hold n_jobs independent embeddings side
+ * by side (one tree per job, built, traversed and stepped in the same
+ * launches).  Job j owns the n_per_job[j] >= 2 consecutive points after
+ * those of jobs 0..j-1 of the concatenated Y; the sum must not exceed n_max.
+ * n_per_job is a host array.  A new tree holds one job of whatever n the
+ * next build is given; after this call every build must be given exactly
+ * the layout's total.  Jobs in one layout see only their own points: their
+ * results are those of the same jobs built and traversed alone. */
+hts_status hts_tree_set_jobs(hts_tree tree, int32_t n_jobs,
+                             const int64_t *n_per_job);
+
+/* Builds the tree of Y (n points, 2 <= n <= n_max) on the stream (one tree
+ * per job of the layout).  The tree keeps its own copy of everything it
+ * needs; Y may change afterwards. */
 hts_status hts_build_polar_tree(hts_ctx ctx, hts_stream stream, const void *Y,
                                 int64_t n, int32_t y_dtype, hts_tree tree);
 
@@ -160,6 +172,20 @@ hts_status hts_gradient_bh(hts_ctx ctx, hts_stream stream, const void *Y,
                            double exaggeration, hts_tree tree, double theta,
                            void *grad, double *z_dev, uint64_t *stats_dev);
 
+/* The same for every job of the tree's layout at once (hts_tree_set_jobs).
+ * Y, grad: the concatenated n x 2 arrays.  P: one CSR over the concatenated
+ * rows whose column indices are global (a job's columns lie in its own
+ * range).  exaggeration_dev: device double[n_jobs], the exaggeration of each
+ * job; z_dev: device double[n_jobs], receives each job's Z.  stats_dev as
+ * above, summed over the jobs.  Each job's gradient and Z equal those of the
+ * job alone through hts_gradient_bh, bit for bit. */
+hts_status hts_gradient_bh_jobs(hts_ctx ctx, hts_stream stream, const void *Y,
+                                int64_t n, int32_t dtype, const int64_t *row_ptr,
+                                const int32_t *col_idx, const void *p_val,
+                                const double *exaggeration_dev, hts_tree tree,
+                                double theta, void *grad, double *z_dev,
+                                uint64_t *stats_dev);
+
 /* ------------------------------------------------------------------------
  * Riemannian step -- eqs. (7), (16)-(18) and the optimiser of Sec. 5.  In
  * place on Y, update and gains (n x 2 each):
@@ -175,6 +201,25 @@ hts_status hts_step(hts_ctx ctx, hts_stream stream, void *Y, void *update,
                     void *gains, const void *grad, int64_t n, int32_t dtype,
                     double eta, double momentum, double min_gain,
                     double boundary_eps, int32_t metric_power);
+
+/* The step for every job of a tree's layout: n must be the layout's total;
+ * eta_dev and momentum_dev are device double[n_jobs] (each job's learning
+ * rate and momentum). */
+hts_status hts_step_jobs(hts_ctx ctx, hts_stream stream, hts_tree tree, void *Y,
+                         void *update, void *gains, const void *grad, int64_t n,
+                         int32_t dtype, const double *eta_dev,
+                         const double *momentum_dev, double min_gain,
+                         double boundary_eps, int32_t metric_power);
+
+/* Optimiser schedule of Sec. 5 per job, on the device: for each of n_jobs
+ * jobs with iteration counter it_dev[j] (device int32), writes
+ * exaggeration_dev[j] = exaggeration and momentum_dev[j] = momentum_early
+ * while it_dev[j] < ee_iters, else 1 and momentum_late; then increments
+ * it_dev[j].  Jobs of one layout may be at different iterations. */
+hts_status hts_jobs_schedule(hts_ctx ctx, hts_stream stream, int32_t n_jobs,
+                             int32_t *it_dev, int32_t ee_iters, double exaggeration,
+                             double momentum_early, double momentum_late,
+                             double *exaggeration_dev, double *momentum_dev);
 
 /* ------------------------------------------------------------------------
  * Kernel timing with HIP events on the caller's stream (for benchmarks).

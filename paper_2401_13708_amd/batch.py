@@ -1,0 +1,115 @@
+"""Many hyperbolic t-SNE embeddings advancing together on one GPU.
+
+The jobs are laid side by side: one concatenated Y (with update, gains,
+gradient), one CSR of P whose column indices are global, and one tree whose
+job layout (`hts_tree_set_jobs`) keeps every job in its own subtree range.
+An iteration of all jobs is then the same four library calls as for one job
+(schedule, tree, Barnes-Hut gradient, step), whatever the number of jobs, and
+each job's result is bit for bit the one it gets alone.
+
+Jobs may be at different iterations of the schedule of Sec. 5 (per-job
+iteration counters on the device), which the serving loop uses when it
+admits new jobs next to running ones.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import hts
+from .embed import Schedule
+
+
+class Job:
+    """One embedding job: its P (CSR, local column indices) and start Y on the device."""
+
+    def __init__(self, row_ptr, col_idx, p_val, Y0, name: str = ""):
+        self.rp, self.col, self.val, self.Y0 = row_ptr, col_idx, p_val, Y0
+        self.n = int(Y0.shape[0])
+        self.name = name
+
+
+class JobBatch:
+    """Device-resident state of several jobs in one layout.
+
+    `start_iter[j]` gives the iteration job j is at (0 for a fresh job); state
+    (Y, update, gains) may be handed over from a previous layout with
+    `carry`, a list of (Y, update, gains) or None per job."""
+
+    def __init__(self, ctx: hts.Context, jobs: list[Job], theta: float = 0.5, max_depth: int = 20,
+                 schedule: Schedule | None = None, start_iter=None, carry=None,
+                 n_max: int | None = None):
+        if not jobs:
+            raise ValueError("a batch needs at least one job")
+        self.ctx, self.jobs, self.theta = ctx, jobs, theta
+        self.sched = schedule or Schedule()
+        dev = jobs[0].Y0.device
+        dt = jobs[0].Y0.dtype
+        sizes = [j.n for j in jobs]
+        self.sizes = sizes
+        self.off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        N = int(self.off[-1])
+        self.N = N
+        # concatenated CSR with global columns
+        rps, cols, vals, nnz0 = [], [], [], 0
+        for j, job in enumerate(jobs):
+            rps.append(job.rp[:-1] + nnz0)
+            cols.append(job.col + int(self.off[j]))
+            vals.append(job.val)
+            nnz0 += int(job.col.numel())
+        rps.append(torch.tensor([nnz0], dtype=torch.int64, device=dev))
+        self.rp = torch.cat(rps).contiguous()
+        self.col = torch.cat(cols).to(torch.int32).contiguous()
+        self.val = torch.cat(vals).contiguous()
+        # state
+        self.Y = torch.empty((N, 2), dtype=dt, device=dev)
+        self.update = torch.zeros_like(self.Y)
+        self.gains = torch.ones_like(self.Y)
+        for j, job in enumerate(jobs):
+            a, b = int(self.off[j]), int(self.off[j + 1])
+            c = carry[j] if carry is not None else None
+            if c is None:
+                self.Y[a:b] = job.Y0
+            else:
+                self.Y[a:b], self.update[a:b], self.gains[a:b] = c
+        self.grad = torch.empty_like(self.Y)
+        J = len(jobs)
+        self.z = torch.zeros(J, dtype=torch.float64, device=dev)
+        it0 = [0] * J if start_iter is None else list(start_iter)
+        self.it = torch.tensor(it0, dtype=torch.int32, device=dev)
+        self.ex = torch.empty(J, dtype=torch.float64, device=dev)
+        self.mu = torch.empty(J, dtype=torch.float64, device=dev)
+        s = self.sched
+        self.eta = torch.tensor([s.eta if s.eta is not None else n / 12000.0 for n in sizes],
+                                dtype=torch.float64, device=dev)
+        self.tree = hts.Tree(ctx, max(N, n_max or 0), max_depth)
+        self.tree.set_jobs(sizes)
+        self.iters_done = 0
+
+    def iterate(self, stats=None):
+        s = self.sched
+        hts.jobs_schedule(self.ctx, self.it, s.ee_iters, s.exaggeration, s.momentum_early,
+                          s.momentum_late, self.ex, self.mu)
+        hts.build_polar_tree(self.ctx, self.Y, self.tree)
+        hts.gradient_bh_jobs(self.ctx, self.Y, self.rp, self.col, self.val, self.tree, self.ex,
+                             self.theta, self.grad, self.z, stats)
+        hts.step_jobs(self.ctx, self.tree, self.Y, self.update, self.gains, self.grad, self.eta,
+                      self.mu, s.min_gain, s.boundary_eps, s.metric_power)
+        self.iters_done += 1
+
+    def run(self, iters: int):
+        for _ in range(iters):
+            self.iterate()
+        return self
+
+    def job_slice(self, j: int) -> slice:
+        return slice(int(self.off[j]), int(self.off[j + 1]))
+
+    def state(self, j: int):
+        sl = self.job_slice(j)
+        return self.Y[sl], self.update[sl], self.gains[sl]
+
+    def close(self):
+        if self.tree is not None:
+            self.tree.close()
+            self.tree = None

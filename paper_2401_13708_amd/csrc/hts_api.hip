@@ -177,17 +177,17 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
     t->max_depth = max_depth;
     t->cap_nodes = cap;
     t->nb = cdiv(n_max, kBlock);
-    int fd = 3;
-    if (const char *e = std::getenv("HTS_FRONTIER_DEPTH")) fd = std::atoi(e);  // tuning knob
-    if (fd < 1) fd = 1;
-    if (fd > 5) fd = 5;
-    t->fdepth = max_depth < fd ? max_depth : fd;
     size_t nm = (size_t)n_max;
+    const size_t nqb_max = (size_t)cdiv(n_max, kWave);
     struct A { void **p; size_t bytes; } allocs[] = {
+        {(void **)&t->job_off, 2 * 8},
+        {(void **)&t->job_qb, 2 * 4},
+        {(void **)&t->qb_job, nqb_max * 4},
+        {(void **)&t->pjob, nm * 4},
+        {(void **)&t->root, 2 * 8},
         {(void **)&t->r, nm * 8},
         {(void **)&t->phi, nm * 8},
-        {(void **)&t->mm, (size_t)t->nb * 16},
-        {(void **)&t->root, 16},
+        {(void **)&t->mm, (size_t)t->nb * 32},
         {(void **)&t->keys_in, nm * 8},
         {(void **)&t->keys, nm * 8},
         {(void **)&t->idx_in, nm * 4},
@@ -202,8 +202,6 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
         {(void **)&t->r_cell, (size_t)cap * 8},
         {(void **)&t->node_first, (size_t)cap * 4},
         {(void **)&t->sinhalf, 32 * 8},
-        {(void **)&t->parent, (size_t)cap * 4},
-        {(void **)&t->frontier, 1024 * 4},
     };
     hts_status s = HTS_OK;
     for (auto &a : allocs) {
@@ -225,6 +223,9 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
         for (int l = 0; l < 32; ++l) sh[l] = l <= 1 ? 1.0 : std::sin(M_PI / std::ldexp(1.0, l));
         hipError_t e = hipMemcpy(t->sinhalf, sh, sizeof(sh), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(t->d_m, 0, 64);
+        // one job: every point and every query block belongs to job 0
+        if (e == hipSuccess) e = hipMemset(t->pjob, 0, nm * 4);
+        if (e == hipSuccess) e = hipMemset(t->qb_job, 0, nqb_max * 4);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) s = hip_fail(e, "tree init");
     }
@@ -240,13 +241,67 @@ hts_status hts_tree_destroy(hts_tree t) {
     if (!t) return fail(HTS_EINVAL, "hts_tree_destroy: tree is NULL");
     hipSetDevice(t->ctx->device);
     hipDeviceSynchronize();
-    void *ptrs[] = {t->r, t->phi, t->mm, t->root, t->keys_in, t->keys, t->idx_in, t->perm,
-                    t->sort_tmp, t->ncnt_part, t->q_part, t->node_start, t->psum, t->d_m,
-                    t->spts, t->nodes, t->r_cell, t->node_first, t->sinhalf, t->parent,
-                    t->frontier};
+    void *ptrs[] = {t->job_off, t->job_qb, t->qb_job, t->pjob, t->root, t->r, t->phi, t->mm,
+                    t->keys_in, t->keys, t->idx_in, t->perm, t->sort_tmp, t->ncnt_part,
+                    t->q_part, t->node_start, t->psum, t->d_m, t->spts, t->nodes, t->r_cell,
+                    t->node_first, t->sinhalf};
     for (void *p : ptrs)
         if (p) hipFree(p);
     delete t;
+    return HTS_OK;
+}
+
+hts_status hts_tree_set_jobs(hts_tree t, int32_t n_jobs, const int64_t *n_per_job) {
+    if (!t) return fail(HTS_EINVAL, "hts_tree_set_jobs: tree is NULL");
+    if (n_jobs < 1 || n_jobs > (1 << 24))
+        return fail(HTS_EINVAL, "hts_tree_set_jobs: n_jobs = %d not in [1, 2^24]", n_jobs);
+    if (!n_per_job) return fail(HTS_EINVAL, "hts_tree_set_jobs: n_per_job is NULL");
+    std::vector<int64_t> off((size_t)n_jobs + 1, 0);
+    std::vector<int32_t> jqb((size_t)n_jobs + 1, 0);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        if (n_per_job[j] < 2)
+            return fail(HTS_EINVAL, "hts_tree_set_jobs: job %d has %lld < 2 points", j,
+                        (long long)n_per_job[j]);
+        off[j + 1] = off[j] + n_per_job[j];
+        if (off[j + 1] > t->n_max)
+            return fail(HTS_EINVAL, "hts_tree_set_jobs: %lld points in all exceed n_max = %lld",
+                        (long long)off[j + 1], (long long)t->n_max);
+        jqb[j + 1] = jqb[j] + (int32_t)cdiv(n_per_job[j], kWave);
+    }
+    const int64_t n = off[n_jobs];
+    const int64_t nqb = jqb[n_jobs];
+    if (nqb > cdiv(t->n_max, kWave) + n_jobs)
+        return fail(HTS_EINVAL, "hts_tree_set_jobs: too many query blocks");
+    std::vector<int32_t> pj((size_t)n), qj((size_t)nqb);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        for (int64_t i = off[j]; i < off[j + 1]; ++i) pj[(size_t)i] = j;
+        for (int32_t b = jqb[j]; b < jqb[j + 1]; ++b) qj[(size_t)b] = j;
+    }
+    HTS_HIP(hipSetDevice(t->ctx->device));
+    HTS_HIP(hipDeviceSynchronize());
+    void **tabs[] = {(void **)&t->job_off, (void **)&t->job_qb, (void **)&t->qb_job,
+                     (void **)&t->root};
+    const size_t bytes[] = {off.size() * 8, jqb.size() * 4,
+                            (size_t)(nqb > cdiv(t->n_max, kWave) ? nqb : cdiv(t->n_max, kWave)) * 4,
+                            (size_t)n_jobs * 16};
+    for (int a = 0; a < 4; ++a) {
+        HTS_HIP(hipFree(*tabs[a]));
+        *tabs[a] = nullptr;
+        HTS_HIP(hipMalloc(tabs[a], bytes[a]));
+    }
+    HTS_HIP(hipMemcpy(t->job_off, off.data(), off.size() * 8, hipMemcpyHostToDevice));
+    HTS_HIP(hipMemcpy(t->job_qb, jqb.data(), jqb.size() * 4, hipMemcpyHostToDevice));
+    HTS_HIP(hipMemcpy(t->qb_job, qj.data(), qj.size() * 4, hipMemcpyHostToDevice));
+    HTS_HIP(hipMemcpy(t->pjob, pj.data(), pj.size() * 4, hipMemcpyHostToDevice));
+    t->J = n_jobs;
+    t->h_off = off;
+    t->nqb = nqb;
+    t->jobs_set = true;
+    t->tab_n = n;
+    int bits = 0;
+    while ((1 << bits) < n_jobs) ++bits;
+    t->job_bits = bits;
+    t->n = 0;  // nothing built for this layout yet
     return HTS_OK;
 }
 
@@ -257,6 +312,9 @@ hts_status hts_build_polar_tree(hts_ctx c, hts_stream stream, const void *Y, int
     if (n < 2 || n > t->n_max)
         return fail(HTS_EINVAL, "hts_build_polar_tree: n = %lld not in [2, n_max = %lld]",
                     (long long)n, (long long)t->n_max);
+    if (t->jobs_set && n != t->h_off.back())
+        return fail(HTS_EINVAL, "hts_build_polar_tree: n = %lld, but the job layout holds %lld points",
+                    (long long)n, (long long)t->h_off.back());
     if (!dtype_ok(y_dtype)) return fail(HTS_EINVAL, "hts_build_polar_tree: bad dtype");
     if (!Y) return fail(HTS_EINVAL, "hts_build_polar_tree: Y is NULL");
     HTS_HIP(hipSetDevice(c->device));
@@ -369,15 +427,28 @@ extern "C" hts_status hts_gradient_exact(hts_ctx c, hts_stream stream, const voi
 
 template <typename T>
 static hts_status bh_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, const int64_t *rp,
-                          const int32_t *col, const T *val, double ex, hts_tree t, double theta,
-                          T *grad, double *z_dev, uint64_t *stats) {
+                          const int32_t *col, const T *val, double ex, const double *ex_job,
+                          hts_tree t, double theta, T *grad, double *z_dev, uint64_t *stats) {
     HTS_OKR(ensure(c->pts, (size_t)n * sizeof(PointRec<T>)));
     HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
     PointRec<T> *pts = (PointRec<T> *)c->pts.p;
     HTS_OKR(tree_thresholds(c, st, t, sizeof(T) == 8 ? HTS_F64 : HTS_F32, theta));
     HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
     HTS_OKR(launch_attract<T>(c, st, pts, rp, col, val, n, (T *)c->fattr.p));
-    return launch_bh_repulsion<T>(c, st, t, n, (const T *)c->fattr.p, ex, grad, z_dev, stats);
+    return launch_bh_repulsion<T>(c, st, t, n, (const T *)c->fattr.p, ex, ex_job, grad, z_dev,
+                                  stats);
+}
+
+static hts_status bh_tree_args(const char *fn, hts_ctx c, hts_tree t, int64_t n, int32_t dtype,
+                               double theta) {
+    if (!(theta >= 0.0) || !std::isfinite(theta))
+        return fail(HTS_EINVAL, "%s: theta %g must be finite and >= 0", fn, theta);
+    if (!t) return fail(HTS_EINVAL, "%s: tree is NULL", fn);
+    if (t->ctx != c) return fail(HTS_EINVAL, "%s: tree belongs to another context", fn);
+    if (t->n != n) return fail(HTS_EINVAL, "%s: tree was built for n = %lld, not %lld", fn,
+                               (long long)t->n, (long long)n);
+    if (t->dtype != dtype) return fail(HTS_EINVAL, "%s: tree built with another dtype", fn);
+    return HTS_OK;
 }
 
 extern "C" {
@@ -387,20 +458,33 @@ hts_status hts_gradient_bh(hts_ctx c, hts_stream stream, const void *Y, int64_t 
                            double *z_dev, uint64_t *stats_dev) {
     HTS_OKR(grad_args("hts_gradient_bh", c, Y, n, dtype, row_ptr, col_idx, p_val, exaggeration,
                       grad, z_dev));
-    if (!(theta >= 0.0) || !std::isfinite(theta))
-        return fail(HTS_EINVAL, "hts_gradient_bh: theta %g must be finite and >= 0", theta);
-    if (!t) return fail(HTS_EINVAL, "hts_gradient_bh: tree is NULL");
-    if (t->ctx != c) return fail(HTS_EINVAL, "hts_gradient_bh: tree belongs to another context");
-    if (t->n != n) return fail(HTS_EINVAL, "hts_gradient_bh: tree was built for n = %lld, not %lld",
-                               (long long)t->n, (long long)n);
-    if (t->dtype != dtype) return fail(HTS_EINVAL, "hts_gradient_bh: tree built with another dtype");
+    HTS_OKR(bh_tree_args("hts_gradient_bh", c, t, n, dtype, theta));
+    if (t->J != 1)
+        return fail(HTS_EINVAL, "hts_gradient_bh: the tree holds %d jobs; use hts_gradient_bh_jobs", t->J);
     HTS_HIP(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     if (dtype == HTS_F64)
         return bh_impl<double>(c, st, (const double *)Y, n, row_ptr, col_idx, (const double *)p_val,
-                               exaggeration, t, theta, (double *)grad, z_dev, stats_dev);
+                               exaggeration, nullptr, t, theta, (double *)grad, z_dev, stats_dev);
     return bh_impl<float>(c, st, (const float *)Y, n, row_ptr, col_idx, (const float *)p_val,
-                          exaggeration, t, theta, (float *)grad, z_dev, stats_dev);
+                          exaggeration, nullptr, t, theta, (float *)grad, z_dev, stats_dev);
+}
+
+hts_status hts_gradient_bh_jobs(hts_ctx c, hts_stream stream, const void *Y, int64_t n,
+                                int32_t dtype, const int64_t *row_ptr, const int32_t *col_idx,
+                                const void *p_val, const double *exaggeration_dev, hts_tree t,
+                                double theta, void *grad, double *z_dev, uint64_t *stats_dev) {
+    HTS_OKR(grad_args("hts_gradient_bh_jobs", c, Y, n, dtype, row_ptr, col_idx, p_val, 1.0, grad,
+                      z_dev));
+    HTS_OKR(bh_tree_args("hts_gradient_bh_jobs", c, t, n, dtype, theta));
+    if (!exaggeration_dev) return fail(HTS_EINVAL, "hts_gradient_bh_jobs: exaggeration_dev is NULL");
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == HTS_F64)
+        return bh_impl<double>(c, st, (const double *)Y, n, row_ptr, col_idx, (const double *)p_val,
+                               1.0, exaggeration_dev, t, theta, (double *)grad, z_dev, stats_dev);
+    return bh_impl<float>(c, st, (const float *)Y, n, row_ptr, col_idx, (const float *)p_val, 1.0,
+                          exaggeration_dev, t, theta, (float *)grad, z_dev, stats_dev);
 }
 
 // ---------------------------------------------------------------- step
@@ -420,11 +504,71 @@ hts_status hts_step(hts_ctx c, hts_stream stream, void *Y, void *update, void *g
     hipStream_t st = (hipStream_t)stream;
     if (dtype == HTS_F64)
         return launch_step<double>(c, st, (double *)Y, (double *)update, (double *)gains,
-                                   (const double *)grad, n, eta, momentum, min_gain, boundary_eps,
-                                   metric_power);
+                                   (const double *)grad, n, eta, momentum, nullptr, nullptr,
+                                   nullptr, min_gain, boundary_eps, metric_power);
     return launch_step<float>(c, st, (float *)Y, (float *)update, (float *)gains,
-                              (const float *)grad, n, eta, momentum, min_gain, boundary_eps,
-                              metric_power);
+                              (const float *)grad, n, eta, momentum, nullptr, nullptr, nullptr,
+                              min_gain, boundary_eps, metric_power);
+}
+
+hts_status hts_step_jobs(hts_ctx c, hts_stream stream, hts_tree t, void *Y, void *update,
+                         void *gains, const void *grad, int64_t n, int32_t dtype,
+                         const double *eta_dev, const double *momentum_dev, double min_gain,
+                         double boundary_eps, int32_t metric_power) {
+    if (!t) return fail(HTS_EINVAL, "hts_step_jobs: tree is NULL");
+    if (!dtype_ok(dtype)) return fail(HTS_EINVAL, "hts_step_jobs: bad dtype");
+    if (t->h_off.empty() || !t->jobs_set || n != t->h_off.back())
+        return fail(HTS_EINVAL, "hts_step_jobs: n = %lld does not match the tree's job layout",
+                    (long long)n);
+    if (!(min_gain >= 0.0)) return fail(HTS_EINVAL, "hts_step_jobs: min_gain < 0");
+    if (!(boundary_eps > 0.0) || !(boundary_eps < 1.0)) return fail(HTS_EINVAL, "hts_step_jobs: boundary_eps not in (0, 1)");
+    if (metric_power != 1 && metric_power != 2) return fail(HTS_EINVAL, "hts_step_jobs: metric_power must be 1 or 2");
+    if (!Y || !update || !gains || !grad || !eta_dev || !momentum_dev)
+        return fail(HTS_EINVAL, "hts_step_jobs: NULL pointer argument");
+    if (!c) return fail(HTS_EINVAL, "hts_step_jobs: ctx is NULL");
+    if (t->ctx != c) return fail(HTS_EINVAL, "hts_step_jobs: tree belongs to another context");
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == HTS_F64)
+        return launch_step<double>(c, st, (double *)Y, (double *)update, (double *)gains,
+                                   (const double *)grad, n, 0.0, 0.0, t->pjob, eta_dev,
+                                   momentum_dev, min_gain, boundary_eps, metric_power);
+    return launch_step<float>(c, st, (float *)Y, (float *)update, (float *)gains,
+                              (const float *)grad, n, 0.0, 0.0, t->pjob, eta_dev, momentum_dev,
+                              min_gain, boundary_eps, metric_power);
+}
+
+// ---------------------------------------------------------------- schedule
+}  // extern "C"
+__global__ void k_jobs_schedule(int32_t J, int32_t *__restrict__ it, int32_t ee_iters, double ex,
+                                double mu_early, double mu_late, double *__restrict__ ex_out,
+                                double *__restrict__ mu_out) {
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= J) return;
+    const int32_t k = it[j];
+    const bool early = k < ee_iters;
+    ex_out[j] = early ? ex : 1.0;
+    mu_out[j] = early ? mu_early : mu_late;
+    it[j] = k + 1;
+}
+
+extern "C" {
+hts_status hts_jobs_schedule(hts_ctx c, hts_stream stream, int32_t n_jobs, int32_t *it_dev,
+                             int32_t ee_iters, double exaggeration, double momentum_early,
+                             double momentum_late, double *exaggeration_dev, double *momentum_dev) {
+    if (!c) return fail(HTS_EINVAL, "hts_jobs_schedule: ctx is NULL");
+    if (n_jobs < 1) return fail(HTS_EINVAL, "hts_jobs_schedule: n_jobs < 1");
+    if (!it_dev || !exaggeration_dev || !momentum_dev)
+        return fail(HTS_EINVAL, "hts_jobs_schedule: NULL pointer argument");
+    if (!(exaggeration > 0.0)) return fail(HTS_EINVAL, "hts_jobs_schedule: exaggeration must be > 0");
+    if (!(momentum_early >= 0.0 && momentum_early < 1.0 && momentum_late >= 0.0 && momentum_late < 1.0))
+        return fail(HTS_EINVAL, "hts_jobs_schedule: momentum not in [0, 1)");
+    HTS_HIP(hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_jobs_schedule, dim3(cdiv(n_jobs, kBlock)), dim3(kBlock), 0,
+                       (hipStream_t)stream, n_jobs, it_dev, ee_iters, exaggeration, momentum_early,
+                       momentum_late, exaggeration_dev, momentum_dev);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
 }
 
 // ---------------------------------------------------------------- timing

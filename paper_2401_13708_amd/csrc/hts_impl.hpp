@@ -50,6 +50,22 @@ constexpr int kNextBits = 26;
 constexpr uint32_t kNextMask = (1u << kNextBits) - 1u;
 constexpr int64_t kMaxNodes = (int64_t)1 << kNextBits;
 
+// Job layout as the kernels see it.  Query block qb of job j covers the
+// global points off[j] + 64 (qb - job_qb[j]) ... (at most 64, within the job).
+struct Jobs {
+    const int64_t *off;
+    const int32_t *job_qb;
+    const int32_t *qb_job;
+    const int32_t *pjob;
+    int32_t J;
+    __device__ __forceinline__ void block(int64_t qb, int64_t &start, int &cnt, int &job) const {
+        job = qb_job[qb];
+        start = off[job] + (int64_t)64 * (qb - job_qb[job]);
+        const int64_t e = off[job + 1] - start;
+        cnt = e < 64 ? (int)e : 64;
+    }
+};
+
 // double-double triple used for the prefix sums of the midpoint summands
 struct DD3 { double hi[3]; double lo[3]; };
 
@@ -85,9 +101,20 @@ struct hts_tree_s {
     int64_t n = 0;            // points of the last build
     int32_t dtype = -1;       // dtype of the last build
     int64_t nb = 0;           // blocks over n_max
+    // job layout: J embeddings side by side, job j owning global points
+    // [off[j], off[j+1]); J = 1 with off = {0, n} unless set explicitly
+    int32_t J = 1;
+    bool jobs_set = false;        // layout given by hts_tree_set_jobs
+    int64_t tab_n = -1;           // n the single-job tables were written for
+    std::vector<int64_t> h_off;   // host copy of off
+    int64_t *job_off = nullptr;   // [J+1]
+    int32_t *job_qb = nullptr;    // [J+1] first query block of each job
+    int32_t *qb_job = nullptr;    // [nqb_max] job of each query block
+    int32_t *pjob = nullptr;      // [n_max] job of each point
+    int64_t nqb = 0;              // query blocks of the layout
+    double *root = nullptr;       // [2J] (r_min, r_max) per job
     double *r = nullptr, *phi = nullptr;
-    double *mm = nullptr;     // per-block (min r, max r)
-    double *root = nullptr;   // (r_min, r_max)
+    double *mm = nullptr;     // per block: (min, max) of its first and of its last job
     uint64_t *keys_in = nullptr, *keys = nullptr;
     uint32_t *idx_in = nullptr, *perm = nullptr;
     void *sort_tmp = nullptr;
@@ -102,9 +129,7 @@ struct hts_tree_s {
     double *r_cell = nullptr;      // [cap_nodes]
     int32_t *node_first = nullptr; // [cap_nodes]
     double *sinhalf = nullptr;     // [32] sin(pi / 2^l), 1 for l <= 1
-    int32_t *parent = nullptr;     // [cap_nodes] parent node (-1 for the root)
-    int32_t *frontier = nullptr;   // [4^fdepth] node of each frontier cell, or -1
-    int32_t fdepth = 0;            // depth of the frontier cells that split the traversal
+    int32_t job_bits = 0;          // key bits above the 2 max_depth cell bits
 };
 
 namespace hts {
@@ -146,6 +171,13 @@ hts_status launch_prep_points(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n
 template <typename T>
 hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tree t);
 
+// device tables of a one-job layout over n points (when n changed)
+hts_status tree_single_job(hipStream_t st, hts_tree t, int64_t n);
+
+inline Jobs jobs_of(hts_tree t) {
+    return Jobs{t->job_off, t->job_qb, t->qb_job, t->pjob, t->J};
+}
+
 hts_status tree_thresholds(hts_ctx ctx, hipStream_t st, hts_tree t, int dtype, double theta);
 
 template <typename T>
@@ -153,9 +185,12 @@ hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, c
                           const int32_t *col, const T *val, int64_t n, T *fattr);
 
 // Barnes-Hut repulsion over the tree and the combine g = 4 (a F_attr - F_rep / Z)
+// ex_job: per-job exaggeration (device, [J]) or NULL for ex; z_dev receives
+// Z of every job ([J])
 template <typename T>
 hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, const T *fattr,
-                               double ex, T *grad, double *z_dev, uint64_t *stats);
+                               double ex, const double *ex_job, T *grad, double *z_dev,
+                               uint64_t *stats);
 
 template <typename T>
 hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,
@@ -166,9 +201,11 @@ hts_status launch_finalize(hts_ctx ctx, hipStream_t st, const T *fattr, const FR
                            const double *zpart, int64_t nz, int64_t n, double ex, T *grad,
                            double *z_dev);
 
+// eta_job / mu_job: per-job values (device, indexed through pjob) or NULL
 template <typename T>
 hts_status launch_step(hts_ctx ctx, hipStream_t st, T *Y, T *U, T *G, const T *grad, int64_t n,
-                       double eta, double mu, double min_gain, double eps, int metric_power);
+                       double eta, double mu, const int32_t *pjob, const double *eta_job,
+                       const double *mu_job, double min_gain, double eps, int metric_power);
 
 hts_status affinities(hts_ctx ctx, hipStream_t st, const void *X, int64_t n, int32_t d,
                       int32_t x_dtype, double perplexity, int32_t k, int32_t *knn_idx,

@@ -47,10 +47,10 @@ struct LdsItem {
 struct alignas(16) ItemRec {
     int32_t node;
     uint32_t nd;
-    int32_t qb;        // query block
-    int32_t pad0;
+    int32_t q0;        // first query point (sorted position) of the block
+    int32_t cnt;       // query points in the block
     uint64_t mask;
-    uint64_t pad1;
+    uint64_t pad;
 };
 
 struct Counters {
@@ -219,24 +219,33 @@ __device__ __forceinline__ void put_stats(uint32_t *__restrict__ sp, const Count
 template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_top(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
-    const PointRec<T> *__restrict__ spts, int64_t n, int64_t nqb, int S,
-    int *__restrict__ item_base, int *__restrict__ nitems_out, T *__restrict__ part0,
-    double *__restrict__ ztop, uint32_t *__restrict__ stats_top, unsigned *__restrict__ dense_count,
-    ItemRec *__restrict__ dense) {
+    const int32_t *__restrict__ node_start, Jobs jb, const PointRec<T> *__restrict__ spts,
+    int64_t nqb, int S, int *__restrict__ item_base, int *__restrict__ nitems_out,
+    T *__restrict__ part0, double *__restrict__ ztop, uint32_t *__restrict__ stats_top,
+    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense) {
     __shared__ LdsItem s_items[kBlock / kWave][kItemCap];
     const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (qb >= nqb) return;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     LdsItem *items = s_items[threadIdx.x / kWave];
-    const int64_t q = qb * kWave + lane;
-    const bool valid = q < n;
-    const PointRec<T> me = spts[valid ? q : 0];
+    int64_t q0;
+    int cnt, job;
+    jb.block(qb, q0, cnt, job);
+    q0 = uniform((int)q0);
+    cnt = uniform(cnt);
+    job = uniform(job);
+    const int64_t q = q0 + lane;
+    const bool valid = lane < cnt;
+    const PointRec<T> me = spts[valid ? q : q0];
     const int M = uniform(*d_m);
+    // the job's tree: the pre-order range from its root to the next job's
+    const int k0 = uniform(node_start[jb.off[job]]);
+    const int k1 = uniform(node_start[jb.off[job + 1]]);
     T fx = 0, fy = 0;
     double z = 0.0;
     Counters c;
     int nitems = 0;
-    walk<T, STATS, true, false>(nodes, M, spts, me, q, lane, 0, M, 0, __ballot(valid), S, items,
+    walk<T, STATS, true, false>(nodes, M, spts, me, q, lane, k0, k1, 0, __ballot(valid), S, items,
                                 nitems, Window<T>{}, fx, fy, z, c);
     // reserve a contiguous run of the item list (one atomic per block; the
     // runs of different blocks may come in any order)
@@ -248,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     __builtin_amdgcn_wave_barrier();
     for (int j = lane; j < nitems; j += kWave) {
         const LdsItem it = items[j];
-        dense[base + j] = ItemRec{it.node, it.nd, (int32_t)qb, 0, it.mask, 0};
+        dense[base + j] = ItemRec{it.node, it.nd, (int32_t)q0, cnt, it.mask, 0};
     }
     if (valid) {
         part0[2 * q] = fx;
@@ -275,11 +284,11 @@ __device__ __forceinline__ ItemRec load_item(const ItemRec *__restrict__ dense, 
     ItemRec u;
     u.node = uniform(r.node);
     u.nd = (uint32_t)uniform((int)r.nd);
-    u.qb = uniform(r.qb);
-    u.pad0 = 0;
+    u.q0 = uniform(r.q0);
+    u.cnt = uniform(r.cnt);
     u.mask = ((uint64_t)(uint32_t)uniform((int)(r.mask >> 32)) << 32) |
              (uint64_t)(uint32_t)uniform((int)r.mask);
-    u.pad1 = 0;
+    u.pad = 0;
     return u;
 }
 
@@ -290,7 +299,7 @@ __device__ __forceinline__ ItemRec load_item(const ItemRec *__restrict__ dense, 
 template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_items(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
-    const PointRec<T> *__restrict__ spts, int64_t n, const unsigned *__restrict__ dense_count,
+    const PointRec<T> *__restrict__ spts, const unsigned *__restrict__ dense_count,
     const ItemRec *__restrict__ dense, T *__restrict__ part, double *__restrict__ zitem,
     uint32_t *__restrict__ stats_items) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
@@ -301,8 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
     if (i >= total) return;
     int dummy = 0;
     ItemRec rec = load_item(dense, i);
-    int64_t q = (int64_t)rec.qb * kWave + lane;
-    PointRec<T> me = spts[q < n ? q : n - 1];
+    PointRec<T> me = spts[lane < rec.cnt ? rec.q0 + lane : rec.q0];
     Window<T> win;
     window_load<T>(win, nodes, rec.node + 1, M, lane);
     ItemRec nrec = rec;
@@ -313,14 +321,14 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
         PointRec<T> nme = me;
         Window<T> nwin = win;
         if (i1 < total) {
-            const int64_t nq = (int64_t)nrec.qb * kWave + lane;
-            nme = spts[nq < n ? nq : n - 1];
+            nme = spts[lane < nrec.cnt ? nrec.q0 + lane : nrec.q0];
             window_load<T>(nwin, nodes, nrec.node + 1, M, lane);
         }
         ItemRec nnrec = nrec;
         if (i2 < total) nnrec = load_item(dense, i2);
 
-        const bool valid = q < n;
+        const int64_t q = (int64_t)rec.q0 + lane;
+        const bool valid = lane < rec.cnt;
         T fx = 0, fy = 0;
         double z = 0.0;
         Counters c;
@@ -342,7 +350,6 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
         i = i1;
         rec = nrec;
         nrec = nnrec;
-        q = (int64_t)rec.qb * kWave + lane;
         me = nme;
         win = nwin;
     }
@@ -355,14 +362,17 @@ template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_gather(
     const T *__restrict__ part0, const double *__restrict__ ztop, const T *__restrict__ part,
     const double *__restrict__ zitem, const int *__restrict__ item_base,
-    const int *__restrict__ nitems_in, int64_t n, int64_t nqb, T *__restrict__ frep,
+    const int *__restrict__ nitems_in, Jobs jb, int64_t nqb, T *__restrict__ frep,
     double *__restrict__ zq, const uint32_t *__restrict__ stats_top,
     const uint32_t *__restrict__ stats_items, unsigned long long *__restrict__ stats) {
     const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (qb >= nqb) return;
     const int lane = (int)(threadIdx.x & (kWave - 1));
-    const int64_t q = qb * kWave + lane;
-    const bool valid = q < n;
+    int64_t q0;
+    int cnt, job;
+    jb.block(qb, q0, cnt, job);
+    const int64_t q = q0 + lane;
+    const bool valid = lane < cnt;
     const int64_t b0 = uniform(item_base[qb]);
     const int ni = uniform(nitems_in[qb]);
     T fx = valid ? part0[2 * q] : (T)0, fy = valid ? part0[2 * q + 1] : (T)0;
@@ -415,30 +425,43 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
     }
 }
 
-// Combine, stage 2: Z = sum of the block totals in block order (repeated by
-// every block), then g_i = 4 (a F_attr,i - F_rep,i / Z) scattered to input order.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_bh_finalize(
-    const T *__restrict__ fattr, const T *__restrict__ frep, const double *__restrict__ zq,
-    int64_t nqb, const uint32_t *__restrict__ perm, int64_t n, double ex, T *__restrict__ grad,
-    double *__restrict__ z_dev, uint32_t *__restrict__ err) {
+// Combine, stage 2: Z of every job = the sum of its block totals in block
+// order (one workgroup per job, a fixed reduction tree) ...
+__global__ __launch_bounds__(kBlock) void k_bh_zjob(const double *__restrict__ zq, Jobs jb,
+                                                    double *__restrict__ zjob,
+                                                    double *__restrict__ z_dev) {
     __shared__ double sh[kBlock];
+    const int j = blockIdx.x;
+    const int64_t a0 = jb.job_qb[j], a1 = jb.job_qb[j + 1];
     double s = 0.0;
-    for (int64_t a = threadIdx.x; a < nqb; a += kBlock) s += zq[a];
+    for (int64_t a = a0 + threadIdx.x; a < a1; a += kBlock) s += zq[a];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    const double Z = sh[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *z_dev = Z;
+    if (threadIdx.x == 0) {
+        zjob[j] = sh[0];
+        z_dev[j] = sh[0];
+    }
+}
+
+// ... then g_i = 4 (a F_attr,i - F_rep,i / Z) scattered to input order
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bh_finalize(
+    const T *__restrict__ fattr, const T *__restrict__ frep, const double *__restrict__ zjob,
+    const int32_t *__restrict__ pjob, const uint32_t *__restrict__ perm, int64_t n, double ex,
+    const double *__restrict__ ex_job, T *__restrict__ grad, uint32_t *__restrict__ err) {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= n) return;
+    // sorted positions of a job cover the same range as its input points
+    const int job = pjob[q];
+    const double a = ex_job ? ex_job[job] : ex;
     const uint32_t i = perm[q];
-    const double inv = 1.0 / Z;
-    const double gx = 4.0 * (ex * (double)fattr[2 * (int64_t)i] - (double)frep[2 * q] * inv);
-    const double gy = 4.0 * (ex * (double)fattr[2 * (int64_t)i + 1] - (double)frep[2 * q + 1] * inv);
+    const double inv = 1.0 / zjob[job];
+    const double gx = 4.0 * (a * (double)fattr[2 * (int64_t)i] - (double)frep[2 * q] * inv);
+    const double gy = 4.0 * (a * (double)fattr[2 * (int64_t)i + 1] - (double)frep[2 * q + 1] * inv);
     const T ox = (T)gx, oy = (T)gy;
     if (!isfinite(ox) || !isfinite(oy)) atomicOr(err, HTS_ERR_NONFINITE_GRAD);
     grad[2 * (int64_t)i] = ox;
@@ -456,21 +479,24 @@ static int item_points() {
 
 template <typename T>
 hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, const T *fattr,
-                               double ex, T *grad, double *z_dev, uint64_t *stats) {
-    const int64_t nqb = cdiv(n, kWave);
+                               double ex, const double *ex_job, T *grad, double *z_dev,
+                               uint64_t *stats) {
+    const int64_t nqb = t->nqb;
+    const Jobs jb = jobs_of(t);
     const int64_t slots = nqb * kItemCap;
     const int S = item_points();
     // workspace: item list, partials, per-block sums
     const size_t b_base = (size_t)nqb * 4, b_nit = (size_t)nqb * 4;
     const size_t b_part0 = (size_t)n * 2 * sizeof(T), b_ztop = (size_t)nqb * 8;
     const size_t b_part = (size_t)slots * kWave * 2 * sizeof(T), b_zitem = (size_t)slots * 8;
-    const size_t b_frep = (size_t)nqb * kWave * 2 * sizeof(T), b_zq = (size_t)nqb * 8;
+    const size_t b_frep = (size_t)n * 2 * sizeof(T), b_zq = (size_t)nqb * 8;
     const size_t b_st = stats ? (size_t)(slots + nqb) * kStats * 4 : 0;
     const size_t b_cnt = 256, b_dense = (size_t)slots * sizeof(ItemRec);
-    constexpr int R = 11;
+    const size_t b_zjob = (size_t)t->J * 8;
+    constexpr int R = 12;
     size_t off[R], tot = 0;
     const size_t sizes[R] = {b_base, b_nit, b_part0, b_ztop, b_part, b_zitem,
-                             b_frep, b_zq, b_st, b_cnt, b_dense};
+                             b_frep, b_zq, b_st, b_cnt, b_dense, b_zjob};
     for (int a = 0; a < R; ++a) {
         off[a] = tot;
         tot += (sizes[a] + 255) & ~(size_t)255;
@@ -489,6 +515,7 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     uint32_t *st_top = stats ? st_items + (size_t)slots * kStats : nullptr;
     unsigned *dense_count = (unsigned *)(base + off[9]);
     ItemRec *dense = (ItemRec *)(base + off[10]);
+    double *zjob = (double *)(base + off[11]);
 
     const NodeRec<T> *nodes = (const NodeRec<T> *)t->nodes;
     const PointRec<T> *spts = (const PointRec<T> *)t->spts;
@@ -499,43 +526,44 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     {
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
         if (stats)
-            hipLaunchKernelGGL((k_bh_top<T, true>), gq, dim3(kBlock), 0, st, nodes, t->d_m, spts,
-                               n, nqb, S, item_base, nitems, part0, ztop, st_top, dense_count,
-                               dense);
+            hipLaunchKernelGGL((k_bh_top<T, true>), gq, dim3(kBlock), 0, st, nodes, t->d_m,
+                               t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
+                               st_top, dense_count, dense);
         else
-            hipLaunchKernelGGL((k_bh_top<T, false>), gq, dim3(kBlock), 0, st, nodes, t->d_m, spts,
-                               n, nqb, S, item_base, nitems, part0, ztop, nullptr, dense_count,
-                               dense);
+            hipLaunchKernelGGL((k_bh_top<T, false>), gq, dim3(kBlock), 0, st, nodes, t->d_m,
+                               t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
+                               nullptr, dense_count, dense);
     }
     {
         TimedScope ts(ctx, st, HTS_K_ITEMS);
         if (stats)
             hipLaunchKernelGGL((k_bh_items<T, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
-                               spts, n, dense_count, dense, part, zitem, st_items);
+                               spts, dense_count, dense, part, zitem, st_items);
         else
             hipLaunchKernelGGL((k_bh_items<T, false>), dim3(gi), dim3(kBlock), 0, st, nodes,
-                               t->d_m, spts, n, dense_count, dense, part, zitem, nullptr);
+                               t->d_m, spts, dense_count, dense, part, zitem, nullptr);
     }
     HTS_HIP(hipGetLastError());
     TimedScope ts(ctx, st, HTS_K_FINALIZE);
     if (stats)
         hipLaunchKernelGGL((k_bh_gather<T, true>), gq, dim3(kBlock), 0, st, part0, ztop, part,
-                           zitem, item_base, nitems, n, nqb, frep, zq, st_top, st_items,
+                           zitem, item_base, nitems, jb, nqb, frep, zq, st_top, st_items,
                            (unsigned long long *)stats);
     else
         hipLaunchKernelGGL((k_bh_gather<T, false>), gq, dim3(kBlock), 0, st, part0, ztop, part,
-                           zitem, item_base, nitems, n, nqb, frep, zq, nullptr, nullptr, nullptr);
+                           zitem, item_base, nitems, jb, nqb, frep, zq, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_bh_zjob, dim3(t->J), dim3(kBlock), 0, st, zq, jb, zjob, z_dev);
     hipLaunchKernelGGL(k_bh_finalize<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,
-                       zq, nqb, t->perm, n, ex, grad, z_dev, ctx->d_err);
+                       zjob, t->pjob, t->perm, n, ex, ex_job, grad, ctx->d_err);
     HTS_HIP(hipGetLastError());
     return HTS_OK;
 }
 
 template hts_status launch_bh_repulsion<float>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                               const float *, double, float *, double *,
-                                               uint64_t *);
+                                               const float *, double, const double *, float *,
+                                               double *, uint64_t *);
 template hts_status launch_bh_repulsion<double>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                                const double *, double, double *, double *,
-                                                uint64_t *);
+                                                const double *, double, const double *, double *,
+                                                double *, uint64_t *);
 
 }  // namespace hts

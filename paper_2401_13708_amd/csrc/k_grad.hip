@@ -229,14 +229,23 @@ hts_status launch_finalize(hts_ctx ctx, hipStream_t st, const T *fattr, const FR
 // Riemannian step with momentum and gains (eqs. (7), (16)-(18), Sec. 5).
 // State is stored in T; the exponential map, the Mobius addition and the
 // projection run in double.
+// Learning rate and momentum are per job when eta_job / mu_job are given.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_step(T *__restrict__ Y, T *__restrict__ U,
                                                  T *__restrict__ G, const T *__restrict__ grad,
-                                                 int64_t n, double eta, double mu, double min_gain,
-                                                 double eps, int metric_power,
+                                                 int64_t n, double eta, double mu,
+                                                 const int32_t *__restrict__ pjob,
+                                                 const double *__restrict__ eta_job,
+                                                 const double *__restrict__ mu_job,
+                                                 double min_gain, double eps, int metric_power,
                                                  uint32_t *__restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    if (pjob) {
+        const int job = pjob[i];
+        eta = eta_job[job];
+        mu = mu_job[job];
+    }
     double y0 = (double)Y[2 * i], y1 = (double)Y[2 * i + 1];
     double a = 1.0 - (y0 * y0 + y1 * y1);
     double s = metric_power == 2 ? a * a * 0.25 : a * 0.5;
@@ -293,10 +302,11 @@ __global__ __launch_bounds__(kBlock) void k_step(T *__restrict__ Y, T *__restric
 
 template <typename T>
 hts_status launch_step(hts_ctx ctx, hipStream_t st, T *Y, T *U, T *G, const T *grad, int64_t n,
-                       double eta, double mu, double min_gain, double eps, int metric_power) {
+                       double eta, double mu, const int32_t *pjob, const double *eta_job,
+                       const double *mu_job, double min_gain, double eps, int metric_power) {
     TimedScope ts(ctx, st, HTS_K_STEP);
     hipLaunchKernelGGL(k_step<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, Y, U, G, grad, n, eta,
-                       mu, min_gain, eps, metric_power, ctx->d_err);
+                       mu, pjob, eta_job, mu_job, min_gain, eps, metric_power, ctx->d_err);
     HTS_HIP(hipGetLastError());
     return HTS_OK;
 }
@@ -313,7 +323,8 @@ hts_status launch_step(hts_ctx ctx, hipStream_t st, T *Y, T *U, T *G, const T *g
                                               const double *, int64_t, int64_t, double, T *,      \
                                               double *);                                         \
     template hts_status launch_step<T>(hts_ctx, hipStream_t, T *, T *, T *, const T *, int64_t,   \
-                                       double, double, double, double, int);
+                                       double, double, const int32_t *, const double *,          \
+                                       const double *, double, double, int);
 HTS_INST(float)
 HTS_INST(double)
 template hts_status launch_finalize<float, double>(hts_ctx, hipStream_t, const float *,

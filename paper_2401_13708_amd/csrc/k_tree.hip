@@ -16,6 +16,11 @@
 // A cell becomes a node when its parent holds two or more points (the same
 // set of cells the insertion build of Sec. 2-D produces), so no insertion
 // order is involved.
+//
+// Several embeddings (jobs) are built in one pass: the job index sits in the
+// key bits above the cell bits, so the sort groups each job's points, no cell
+// spans two jobs, and the pre-order array is the concatenation of the jobs'
+// trees.  Every job has its own root annulus.
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "hts_impl.hpp"
@@ -26,13 +31,24 @@ namespace hts {
 constexpr double kTwoPi = 2.0 * 3.14159265358979323846;
 
 // ---------------------------------------------------------------- 1. polar
+// Polar position of every point, and the radial range of every job: a job
+// that lies inside one block is reduced here completely; for the others the
+// block leaves the (min, max) of its first and of its last job's points in mm
+// (segmented scan over the block, jobs being contiguous).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_polar(const T *__restrict__ Y, int64_t n,
+                                                  const int32_t *__restrict__ pjob,
+                                                  const int64_t *__restrict__ job_off,
                                                   double *__restrict__ r, double *__restrict__ phi,
-                                                  double *__restrict__ mm) {
+                                                  double *__restrict__ mm,
+                                                  double *__restrict__ root) {
     __shared__ double smin[kBlock], smax[kBlock];
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ int sjob[kBlock];
+    const int t = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t i = b0 + t;
     double vmin = __builtin_inf(), vmax = -__builtin_inf();
+    int job = -1;
     if (i < n) {
         // position of the single-precision coordinates; products are exact
         double x = (double)(float)Y[2 * i], y = (double)(float)Y[2 * i + 1];
@@ -42,56 +58,82 @@ __global__ __launch_bounds__(kBlock) void k_polar(const T *__restrict__ Y, int64
         r[i] = rr;
         phi[i] = p;
         vmin = vmax = rr;
+        job = pjob[i];
     }
-    smin[threadIdx.x] = vmin;
-    smax[threadIdx.x] = vmax;
+    smin[t] = vmin;
+    smax[t] = vmax;
+    sjob[t] = job;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
-            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
-        }
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const bool take = t >= o && sjob[t - o] == job;
+        const double pa = take ? smin[t - o] : __builtin_inf();
+        const double pb = take ? smax[t - o] : -__builtin_inf();
+        __syncthreads();
+        smin[t] = fmin(smin[t], pa);
+        smax[t] = fmax(smax[t], pb);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        mm[2 * blockIdx.x] = smin[0];
-        mm[2 * blockIdx.x + 1] = smax[0];
+    if (job < 0) return;
+    const bool last = t == kBlock - 1 || sjob[t + 1] != job;
+    if (!last) return;
+    const int64_t b1 = b0 + kBlock < n ? b0 + kBlock : n;
+    const int64_t j0 = job_off[job], j1 = job_off[job + 1];
+    if (j0 >= b0 && j1 <= b1) {
+        root[2 * job] = smin[t];
+        root[2 * job + 1] = smax[t];
+        return;
+    }
+    if (j0 < b0) {  // the block's first job
+        mm[4 * blockIdx.x] = smin[t];
+        mm[4 * blockIdx.x + 1] = smax[t];
+    }
+    if (j1 > b1 || i == b1 - 1) {  // the block's last job
+        mm[4 * blockIdx.x + 2] = smin[t];
+        mm[4 * blockIdx.x + 3] = smax[t];
+    }
+}
+
+// one wave per job that spans several blocks: its range from the partials
+__global__ __launch_bounds__(kBlock) void k_root(const int64_t *__restrict__ job_off, int J,
+                                                 const double *__restrict__ mm,
+                                                 double *__restrict__ root) {
+    const int j = (int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
+    if (j >= J) return;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int64_t b0 = job_off[j] / kBlock, b1 = (job_off[j + 1] - 1) / kBlock;
+    if (b0 == b1) return;  // reduced in k_polar
+    double vmin = __builtin_inf(), vmax = -__builtin_inf();
+    for (int64_t b = b0 + lane; b <= b1; b += kWave) {
+        const int h = b == b0 ? 2 : 0;  // the job is the last one of block b0, the first of the rest
+        vmin = fmin(vmin, mm[4 * b + h]);
+        vmax = fmax(vmax, mm[4 * b + h + 1]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        vmin = fmin(vmin, __shfl_xor(vmin, o, 64));
+        vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
+    }
+    if (lane == 0) {
+        root[2 * j] = vmin;
+        root[2 * j + 1] = vmax;
     }
 }
 
 // ---------------------------------------------------------------- 2. keys
+// job index above max_depth levels of the split rule, two bits per level
+// (radial bit: r >= (lo + hi) / 2 of eq. (10); angular bit: phi >= (lo + hi) / 2)
 __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
                                                  const double *__restrict__ phi, int64_t n,
-                                                 const double *__restrict__ mm, int nbm, int L,
+                                                 const int32_t *__restrict__ pjob,
+                                                 const double *__restrict__ root, int L,
                                                  uint64_t *__restrict__ keys,
-                                                 uint32_t *__restrict__ idx,
-                                                 double *__restrict__ root) {
-    __shared__ double smin[kBlock], smax[kBlock];
-    double vmin = __builtin_inf(), vmax = -__builtin_inf();
-    for (int b = threadIdx.x; b < nbm; b += kBlock) {
-        vmin = fmin(vmin, mm[2 * b]);
-        vmax = fmax(vmax, mm[2 * b + 1]);
-    }
-    smin[threadIdx.x] = vmin;
-    smax[threadIdx.x] = vmax;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
-            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
-        }
-        __syncthreads();
-    }
-    double rmin = smin[0], rmax = smax[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        root[0] = rmin;
-        root[1] = rmax;
-    }
+                                                 uint32_t *__restrict__ idx) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    const int job = pjob[i];
     double rv = r[i], pv = phi[i];
-    double lo = rmin, hi = rmax, plo = 0.0, phh = kTwoPi;
-    uint64_t key = 0;
+    double lo = root[2 * job], hi = root[2 * job + 1], plo = 0.0, phh = kTwoPi;
+    uint64_t key = (uint64_t)job;
     for (int l = 0; l < L; ++l) {
         double mr = __dmul_rn(__dadd_rn(lo, hi), 0.5);
         double mp = __dmul_rn(__dadd_rn(plo, phh), 0.5);
@@ -105,14 +147,16 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
 }
 
 // number of equal leading levels of two keys
+// (-1 for points of different jobs, which share no cell, not even a root)
 __device__ __forceinline__ int lcp_levels(uint64_t a, uint64_t b, int L) {
     uint64_t x = a ^ b;
     if (x == 0) return L;
+    if (x >> (2 * L)) return -1;
     return (__clzll((long long)x) - (64 - 2 * L)) >> 1;
 }
 
 // nodes starting at sorted position i: depths s..D with s = lcp(i-1, i) + 1
-// (0 for i = 0) and D = min(L, max(lcp with either neighbour) + 1), the depth
+// (0 for a job's first point) and D = min(L, max(lcp with either neighbour) + 1), the depth
 // at which the point's cell holds it alone (or the depth cap).
 struct NodeSpan { int s, D; };
 __device__ __forceinline__ NodeSpan node_span(const uint64_t *__restrict__ keys, int64_t i, int64_t n,
@@ -189,10 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt
                                                        int32_t *__restrict__ node_start,
                                                        DD3 *__restrict__ psum, int64_t n,
                                                        int32_t *__restrict__ d_m, int64_t cap,
-                                                       uint32_t *__restrict__ err,
-                                                       int32_t *__restrict__ frontier, int nslots) {
+                                                       uint32_t *__restrict__ err) {
     __shared__ int scnt[kBlock];
-    for (int a = threadIdx.x; a < nslots; a += kBlock) frontier[a] = -1;
     __shared__ DD3 sq[kBlock];
     int64_t per = cdiv(nb, kBlock);
     int64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
@@ -287,12 +329,12 @@ __device__ __forceinline__ double dd_diff(const DD3 &a, const DD3 &b, int c) {
 // first position j > i whose key differs from keys[i] in the first l levels
 __device__ __forceinline__ int64_t cell_end(const uint64_t *__restrict__ keys, int64_t i, int64_t n,
                                             int l, int L) {
-    int sh = 2 * (L - l);
-    uint64_t pre = sh >= 64 ? 0 : (keys[i] >> sh);
+    const int sh = 2 * (L - l);  // the prefix keeps the job bits
+    const uint64_t pre = keys[i] >> sh;
     int64_t lo = i + 1, hi = n;  // answer in [lo, hi]
     while (lo < hi) {
         int64_t mid = lo + ((hi - lo) >> 1);
-        uint64_t pm = sh >= 64 ? 0 : (keys[mid] >> sh);
+        uint64_t pm = keys[mid] >> sh;
         if (pm == pre) lo = mid + 1; else hi = mid;
     }
     return lo;
@@ -308,9 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
                                                  NodeRec<T> *__restrict__ nodes,
                                                  double *__restrict__ r_cell,
                                                  int32_t *__restrict__ node_first,
-                                                 int64_t cap, uint32_t *__restrict__ err,
-                                                 int32_t *__restrict__ parent,
-                                                 int32_t *__restrict__ frontier, int F) {
+                                                 int64_t cap, uint32_t *__restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     NodeSpan sp = node_span(keys, i, n, L);
@@ -318,7 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
     int32_t M = node_start[n];
     int32_t base = node_start[i];
     uint64_t key = keys[i];
-    double lo = root[0], hi = root[1];
+    const int64_t job = (int64_t)(key >> (2 * L));
+    double lo = root[2 * job], hi = root[2 * job + 1];
     int lev = 0;  // levels replayed into (lo, hi)
     for (int l = sp.s; l <= sp.D; ++l) {
         int32_t k = base + (l - sp.s);
@@ -353,30 +394,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
         rec.c = leaf ? __longlong_as_double((long long)i) : 0.0;
         nodes[k] = rec;
         node_first[k] = (int32_t)i;
-        // parent: the previous node at this position, or the depth-(l-1) node
-        // starting at the first point of the enclosing cell
-        int32_t par = -1;
-        if (l > sp.s) {
-            par = k - 1;
-        } else if (l > 0) {
-            const int sh = 2 * (L - (l - 1));
-            const uint64_t pre = sh >= 64 ? 0 : (key >> sh);
-            int64_t lo2 = 0, hi2 = i;  // first j with the same depth-(l-1) prefix
-            while (lo2 < hi2) {
-                int64_t mid = lo2 + ((hi2 - lo2) >> 1);
-                uint64_t pm = sh >= 64 ? 0 : (keys[mid] >> sh);
-                if (pm < pre) lo2 = mid + 1; else hi2 = mid;
-            }
-            const int s0 = lo2 > 0 ? lcp_levels(keys[lo2 - 1], keys[lo2], L) + 1 : 0;
-            par = node_start[lo2] + (l - 1 - s0);
-        }
-        parent[k] = par;
-        // frontier cell: depth F, or a leaf above it; its slot is its key
-        // prefix padded to F levels
-        if (l == F || (l < F && leaf)) {
-            const uint64_t pre = key >> (2 * (L - l));
-            frontier[pre << (2 * (F - l))] = k;
-        }
         // radial bounds of the cell (same arithmetic as the keys)
         while (lev < l) {
             int rb = (int)((key >> (2 * (L - 1 - lev) + 1)) & 1u);
@@ -418,25 +435,48 @@ __global__ __launch_bounds__(kBlock) void k_threshold(NodeRec<T> *__restrict__ n
     nodes[k].c = c;
 }
 
+__global__ void k_single_job(int64_t *__restrict__ job_off, int32_t *__restrict__ job_qb,
+                             int64_t n) {
+    if (threadIdx.x == 0) {
+        job_off[0] = 0;
+        job_off[1] = n;
+        job_qb[0] = 0;
+        job_qb[1] = (int32_t)cdiv(n, kWave);
+    }
+}
+
+hts_status tree_single_job(hipStream_t st, hts_tree t, int64_t n) {
+    if (t->jobs_set || t->tab_n == n) return HTS_OK;
+    hipLaunchKernelGGL(k_single_job, dim3(1), dim3(kWave), 0, st, t->job_off, t->job_qb, n);
+    HTS_HIP(hipGetLastError());
+    t->tab_n = n;
+    t->nqb = cdiv(n, kWave);
+    return HTS_OK;
+}
+
 template <typename T>
 hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tree t) {
     TimedScope ts(ctx, st, HTS_K_TREE);
+    HTS_OKR(tree_single_job(st, t, n));
     const int L = t->max_depth;
     const int64_t nb = cdiv(n, kBlock);
-    hipLaunchKernelGGL(k_polar<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->r, t->phi, t->mm);
+    hipLaunchKernelGGL(k_polar<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->pjob, t->job_off, t->r,
+                       t->phi, t->mm, t->root);
     HTS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kBlock), 0, st, t->r, t->phi, n, t->mm, (int)nb, L,
-                       t->keys_in, t->idx_in, t->root);
+    hipLaunchKernelGGL(k_root, dim3(cdiv(t->J, kBlock / kWave)), dim3(kBlock), 0, st, t->job_off,
+                       t->J, t->mm, t->root);
+    HTS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kBlock), 0, st, t->r, t->phi, n, t->pjob, t->root, L,
+                       t->keys_in, t->idx_in);
     HTS_HIP(hipGetLastError());
     size_t bytes = t->sort_tmp_bytes;
     HTS_HIP(rocprim::radix_sort_pairs(t->sort_tmp, bytes, t->keys_in, t->keys, t->idx_in, t->perm,
-                                      (size_t)n, 0u, (unsigned)(2 * L), st));
+                                      (size_t)n, 0u, (unsigned)(2 * L + t->job_bits), st));
     hipLaunchKernelGGL(k_sorted<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->keys, t->perm, L,
                        (PointRec<T> *)t->spts, t->node_start, t->psum, t->ncnt_part, t->q_part);
     HTS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, st, t->ncnt_part, t->q_part, nb,
-                       t->node_start, t->psum, n, t->d_m, t->cap_nodes, ctx->d_err, t->frontier,
-                       1 << (2 * t->fdepth));
+                       t->node_start, t->psum, n, t->d_m, t->cap_nodes, ctx->d_err);
     HTS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, st, t->node_start, t->psum, n,
                        t->ncnt_part, t->q_part);
@@ -444,18 +484,20 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     hipLaunchKernelGGL(k_emit<T>, dim3(nb), dim3(kBlock), 0, st, t->keys, n, L,
                        (const PointRec<T> *)t->spts, t->node_start, t->psum, t->root, t->sinhalf,
                        (NodeRec<T> *)t->nodes, t->r_cell, t->node_first, t->cap_nodes,
-                       ctx->d_err, t->parent, t->frontier, t->fdepth);
+                       ctx->d_err);
     HTS_HIP(hipGetLastError());
     t->n = n;
     t->dtype = sizeof(T) == 8 ? HTS_F64 : HTS_F32;
     return HTS_OK;
 }
 
+// temporary storage of the sort, sized for the widest key (cell bits plus
+// up to 24 job bits)
 hts_status tree_sort_bytes(int64_t n_max, int L, size_t *bytes) {
     *bytes = 0;
     HTS_HIP(rocprim::radix_sort_pairs(nullptr, *bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
                                       (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n_max, 0u,
-                                      (unsigned)(2 * L), (hipStream_t)0));
+                                      (unsigned)(2 * L + 24), (hipStream_t)0));
     return HTS_OK;
 }
 

@@ -47,6 +47,11 @@ _SIGS = {
     "hts_gradient_exact": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _P]),
     "hts_gradient_bh": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _D, _P, _P, _P]),
     "hts_step": (C.c_int, [_P, _P, _P, _P, _P, _P, _I64, _I32, _D, _D, _D, _D, _I32]),
+    "hts_tree_set_jobs": (C.c_int, [_P, _I32, C.POINTER(_I64)]),
+    "hts_gradient_bh_jobs": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _D, _P, _P,
+                                       _P]),
+    "hts_step_jobs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _I32, _P, _P, _D, _D, _I32]),
+    "hts_jobs_schedule": (C.c_int, [_P, _P, _I32, _P, _I32, _D, _D, _D, _P, _P]),
     "hts_timing_enable": (C.c_int, [_P, _I32]),
     "hts_timing_read": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_I64)]),
 }
@@ -159,6 +164,12 @@ class Tree:
         self.n_max = n_max
         self.max_depth = max_depth
 
+    def set_jobs(self, sizes):
+        """Job layout: len(sizes) embeddings of these sizes, side by side."""
+        arr = (C.c_int64 * len(sizes))(*[int(v) for v in sizes])
+        _ck(lib().hts_tree_set_jobs(self.h, len(sizes), arr))
+        self.jobs = [int(v) for v in sizes]
+
     def close(self):
         if getattr(self, "h", None):
             lib().hts_tree_destroy(self.h)
@@ -258,3 +269,49 @@ def step(ctx: Context, Y, update, gains, grad, eta: float, momentum: float,
     _ck(lib().hts_step(ctx.h, _stream(stream), _ptr(Y), _ptr(update), _ptr(gains), _ptr(grad),
                        Y.shape[0], _dtype(Y), float(eta), float(momentum), float(min_gain),
                        float(boundary_eps), int(metric_power)))
+
+
+def gradient_bh_jobs(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, exaggeration,
+                     theta: float = 0.5, grad=None, z=None, stats=None, stream=None):
+    """Barnes-Hut gradient of every job of the tree's layout; exaggeration
+    and z are device float64 tensors with one entry per job."""
+    _dev(Y, "Y")
+    _csr_args(Y, row_ptr, col_idx, p_val)
+    nj = len(tree.jobs)
+    _dev(exaggeration, "exaggeration", torch.float64)
+    if exaggeration.numel() != nj:
+        raise ValueError("exaggeration needs one entry per job")
+    grad = torch.empty_like(Y) if grad is None else grad
+    z = torch.empty(nj, dtype=torch.float64, device=Y.device) if z is None else z
+    if stats is not None:
+        _dev(stats, "stats", torch.int64)
+        if stats.numel() < 10:
+            raise ValueError("stats needs 10 int64 entries")
+    _ck(lib().hts_gradient_bh_jobs(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
+                                   _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), _ptr(exaggeration),
+                                   tree.h, float(theta), _ptr(grad), _ptr(z), _ptr(stats)))
+    return grad, z
+
+
+def step_jobs(ctx: Context, tree: Tree, Y, update, gains, grad, eta, momentum,
+              min_gain: float = 0.01, boundary_eps: float = 1e-5, metric_power: int = 2,
+              stream=None):
+    """Riemannian step of every job; eta and momentum: device float64, one per job."""
+    for t, nm in ((Y, "Y"), (update, "update"), (gains, "gains"), (grad, "grad")):
+        _dev(t, nm, Y.dtype)
+    for t, nm in ((eta, "eta"), (momentum, "momentum")):
+        _dev(t, nm, torch.float64)
+    _ck(lib().hts_step_jobs(ctx.h, _stream(stream), tree.h, _ptr(Y), _ptr(update), _ptr(gains),
+                            _ptr(grad), Y.shape[0], _dtype(Y), _ptr(eta), _ptr(momentum),
+                            float(min_gain), float(boundary_eps), int(metric_power)))
+
+
+def jobs_schedule(ctx: Context, it, ee_iters: int, exaggeration: float, momentum_early: float,
+                  momentum_late: float, ex_out, mu_out, stream=None):
+    """Per-job optimiser schedule on the device; advances the int32 counters it."""
+    _dev(it, "it", torch.int32)
+    _dev(ex_out, "ex_out", torch.float64)
+    _dev(mu_out, "mu_out", torch.float64)
+    _ck(lib().hts_jobs_schedule(ctx.h, _stream(stream), it.numel(), _ptr(it), int(ee_iters),
+                                float(exaggeration), float(momentum_early), float(momentum_late),
+                                _ptr(ex_out), _ptr(mu_out)))
