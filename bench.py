@@ -88,6 +88,168 @@ def cpu_baseline(n, seconds, theta):
                       "queries" % (it, theta, n, int(rp[-1]), el)}
 
 
+def _job_set(ctx, dev, count, seed, n_lo, n_hi, dims, iters_note=""):
+    """Jobs of uneven size: N log-uniform in [n_lo, n_hi]; data per job from
+    the generator of its workload; P built on the GPU (not timed)."""
+    import numpy as np
+    import torch
+    from paper_2401_13708_amd import hts, synth
+    from paper_2401_13708_amd.batch import Job
+    g = np.random.default_rng(seed)
+    sizes = np.round(np.exp(g.uniform(np.log(n_lo), np.log(n_hi), size=count))).astype(int)
+    clusters = g.integers(5, 21, size=count)
+    dsel = g.choice(dims, size=count)
+    jobs = []
+    for j, n in enumerate(sizes):
+        X = synth.gaussian_mixture(int(n), int(dsel[j]), n_clusters=int(clusters[j]),
+                                   seed=seed + j).astype(np.float32)
+        _, rp, col, val = hts.build_affinities(ctx, torch.from_numpy(X).to(dev), 30.0, 90,
+                                               p_dtype=torch.float32, want_knn=False)
+        Y0 = torch.from_numpy(synth.disk_uniform(int(n), 1e-4, seed=seed + j + 10 ** 6)).to(dev)
+        jobs.append(Job(rp, col, val, Y0, name="job%d" % j))
+    return jobs
+
+
+def bench_jobs(args):
+    """64 jobs of uneven size: all advanced together in one job layout, against
+    the same jobs run one after another with the single-job calls."""
+    import numpy as np
+    import torch
+    from paper_2401_13708_amd import hts
+    from paper_2401_13708_amd.batch import JobBatch, autotune_item_points
+    from paper_2401_13708_amd.embed import Embedding
+    dev = torch.device("cuda", 0)
+    ctx = hts.Context(0)
+    t0 = time.perf_counter()
+    jobs = _job_set(ctx, dev, args.jobs, 400, 500, 50000, [50])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    total_n = sum(j.n for j in jobs)
+    print("bench: %d jobs, %d points in all, set up in %.1fs" % (len(jobs), total_n, setup_s),
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    best, table = autotune_item_points(ctx, jobs, theta=args.theta)
+    tune_s = time.perf_counter() - t0
+    print("bench: work-item size %d (ms/iteration %s)" % (best, {k: round(v, 3) for k, v in table.items()}),
+          file=sys.stderr, flush=True)
+    # one job at a time through the single-job calls
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    finals = []
+    for job in jobs:
+        e = Embedding(ctx, job.rp, job.col, job.val, job.Y0, theta=args.theta)
+        e.run(args.job_iters)
+        finals.append(e.Y)
+        e.close()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    print("bench: sequential %.2fs" % t_seq, file=sys.stderr, flush=True)
+    # all jobs in one layout
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = JobBatch(ctx, jobs, theta=args.theta)
+    b.run(args.job_iters)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    if ctx.check() != 0:
+        raise RuntimeError("device error word set")
+    diff = max(float((b.state(j)[0] - finals[j]).abs().max()) for j in range(len(jobs)))
+    print("bench: batched %.2fs, max |dY| vs sequential %g" % (t_batch, diff), file=sys.stderr,
+          flush=True)
+    b.close()
+    value = len(jobs) / t_batch
+    out = {
+        "metric": "jobs/sec: %d uneven hyperbolic t-SNE jobs in one job layout vs one at a time"
+                  % len(jobs),
+        "value": round(value, 3), "unit": "jobs/s", "n_gpus": 1, "steps": args.job_iters,
+        "warmup": 0, "ms_per_step": round(1000.0 * t_batch / args.job_iters, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%d jobs, N log-uniform in [500, 50000] (%d points in all), D=50 "
+                               "Gaussian mixtures of 5-20 clusters, perplexity 30, k=90, theta=%.2f, "
+                               "%d iterations each (schedule of Sec. 5)"
+                               % (len(jobs), total_n, args.theta, args.job_iters),
+                   "jobs": len(jobs), "sizes": [j.n for j in jobs]},
+        "sequential_jobs_per_s": round(len(jobs) / t_seq, 3),
+        "speedup_vs_sequential": round(t_seq / t_batch, 2),
+        "max_abs_diff_vs_sequential": diff,
+        "autotune": {"item_points": best, "ms_per_iteration": {str(k): round(v, 4) for k, v in table.items()},
+                     "tune_s": round(tune_s, 2)},
+        "setup_s": round(setup_s, 2),
+        "roofline": None, "cpu_baseline": None,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals of jobs of uneven size served by the continuous-
+    batching server, against the same arrivals served one job at a time."""
+    import numpy as np
+    import torch
+    from paper_2401_13708_amd import hts, synth
+    from paper_2401_13708_amd.serve import FifoServer, Request, Server, summarize
+    dev = torch.device("cuda", 0)
+    ctx = hts.Context(0)
+    count = args.serve_jobs
+    g = np.random.default_rng(5)
+    sizes = np.round(np.exp(g.uniform(np.log(1000), np.log(100000), size=count))).astype(int)
+    dims = g.choice([32, 50, 100], size=count)
+    t0 = time.perf_counter()
+    reqs = []
+    for j in range(count):
+        n = int(sizes[j])
+        depth = int(min(10, max(3, np.ceil(np.log2(n / 100.0)))))
+        X = synth.branching_walk(n, int(dims[j]), depth=depth, seed=500 + j).astype(np.float32)
+        reqs.append(Request(j, 0.0, X, iters=args.serve_iters, seed=500 + j + 10 ** 6))
+    gen_s = time.perf_counter() - t0
+    print("bench: %d requests generated in %.1fs (%d points in all)" % (count, gen_s, int(sizes.sum())),
+          file=sys.stderr, flush=True)
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    # capacity: a burst of the first requests, all there at once
+    burst = [Request(r.rid, 0.0, r.X, r.iters, r.seed) for r in reqs[:args.calib_jobs]]
+    srv = Server(ctx, budget, theta=args.theta)
+    cal = summarize(srv.run(burst))
+    cap = cal["jobs_per_s"]
+    rate = args.arrival_rate if args.arrival_rate > 0 else 0.8 * cap
+    arr = np.cumsum(np.random.default_rng(5 + 1).exponential(1.0 / rate, size=count))
+    arr -= arr[0]
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    print("bench: burst capacity %.2f jobs/s; arrival rate %.2f jobs/s" % (cap, rate),
+          file=sys.stderr, flush=True)
+    srv = Server(ctx, budget, theta=args.theta)
+    got = srv.run(reqs)
+    sb = summarize(got, skip=16)
+    print("bench: served %s" % sb, file=sys.stderr, flush=True)
+    fifo = summarize(FifoServer(ctx, theta=args.theta).run(reqs), skip=16)
+    print("bench: one at a time %s" % fifo, file=sys.stderr, flush=True)
+    out = {
+        "metric": "served jobs/sec and p50/p99 completion latency, Poisson arrivals, continuous "
+                  "batching vs one job at a time",
+        "value": round(sb["jobs_per_s"], 3), "unit": "jobs/s", "n_gpus": 1,
+        "steps": args.serve_iters, "warmup": 16, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%d requests, Poisson arrivals at %.2f jobs/s (0.8 x burst capacity "
+                               "unless given), N log-uniform in [1000, 100000], D in {32, 50, 100}, "
+                               "branching-walk data of depth ceil(log2(N/100)) in [3, 10], "
+                               "perplexity 30, k=90, theta=%.2f, %d iterations each, first 16 "
+                               "excluded, HBM budget %.1f GiB"
+                               % (count, rate, args.theta, args.serve_iters, args.hbm_budget_gb),
+                   "requests": count, "arrival_rate": rate},
+        "p50_latency_s": round(sb["p50_latency_s"], 3),
+        "p99_latency_s": round(sb["p99_latency_s"], 3),
+        "one_at_a_time": {k: round(v, 3) for k, v in fifo.items()},
+        "speedup_jobs_per_s": round(sb["jobs_per_s"] / fifo["jobs_per_s"], 2),
+        "max_active_jobs": srv.max_active, "relayouts": srv.relayouts,
+        "burst_capacity_jobs_per_s": round(cap, 3),
+        "roofline": None, "cpu_baseline": None,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,12 +265,26 @@ def main():
     ap.add_argument("--no-stats", action="store_true", help="time without traversal counters")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for PMC calibration)")
+    ap.add_argument("--workload", choices=["single", "jobs", "serve"], default="single",
+                    help="single: the N=70k iteration (default); jobs: 64 uneven jobs batched; "
+                         "serve: Poisson arrivals through the continuous-batching server")
+    ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--job-iters", type=int, default=1000)
+    ap.add_argument("--serve-jobs", type=int, default=256)
+    ap.add_argument("--serve-iters", type=int, default=500)
+    ap.add_argument("--calib-jobs", type=int, default=24)
+    ap.add_argument("--arrival-rate", type=float, default=0.0)
+    ap.add_argument("--hbm-budget-gb", type=float, default=32.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the library runs on one GPU; --gpus %d (WORLD_SIZE %s) is not "
               "supported: sharding by query rows across GPUs is not implemented"
               % (args.gpus, os.environ.get("WORLD_SIZE", "1")), file=sys.stderr)
         sys.exit(2)
+    if args.workload == "jobs":
+        return bench_jobs(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

@@ -38,7 +38,7 @@ class JobBatch:
 
     def __init__(self, ctx: hts.Context, jobs: list[Job], theta: float = 0.5, max_depth: int = 20,
                  schedule: Schedule | None = None, start_iter=None, carry=None,
-                 n_max: int | None = None):
+                 n_max: int | None = None, tree: hts.Tree | None = None):
         if not jobs:
             raise ValueError("a batch needs at least one job")
         self.ctx, self.jobs, self.theta = ctx, jobs, theta
@@ -82,7 +82,13 @@ class JobBatch:
         s = self.sched
         self.eta = torch.tensor([s.eta if s.eta is not None else n / 12000.0 for n in sizes],
                                 dtype=torch.float64, device=dev)
-        self.tree = hts.Tree(ctx, max(N, n_max or 0), max_depth)
+        # a tree of a previous layout is reused when it is large enough
+        if tree is not None and tree.n_max >= N and tree.max_depth == max_depth:
+            self.tree = tree
+        else:
+            if tree is not None:
+                tree.close()
+            self.tree = hts.Tree(ctx, max(N, n_max or 0), max_depth)
         self.tree.set_jobs(sizes)
         self.iters_done = 0
 
@@ -109,7 +115,44 @@ class JobBatch:
         sl = self.job_slice(j)
         return self.Y[sl], self.update[sl], self.gains[sl]
 
+    def release_tree(self) -> hts.Tree:
+        """Hands the tree to the next layout."""
+        t, self.tree = self.tree, None
+        return t
+
     def close(self):
         if self.tree is not None:
             self.tree.close()
             self.tree = None
+
+
+def autotune_item_points(ctx: hts.Context, jobs: list[Job], candidates=(128, 256, 512, 1024, 2048),
+                         warm: int = 100, reps: int = 8, theta: float = 0.5) -> tuple[int, dict]:
+    """Picks the Barnes-Hut work-item size for a batch of jobs by timing.
+
+    A scratch copy of the batch is advanced `warm` iterations (the embedding
+    spreads out, which changes the traversal), then every candidate times
+    `reps` iterations from that same state.  The fastest is set on ctx and
+    returned with the per-candidate milliseconds per iteration."""
+    b = JobBatch(ctx, jobs, theta=theta)
+    prev = getattr(ctx, "item_points", 512)
+    ctx.set_item_points(512)
+    b.run(warm)
+    saved = [t.clone() for t in (b.Y, b.update, b.gains, b.it)]
+    times = {}
+    for S in candidates:
+        ctx.set_item_points(S)
+        for t, v in zip((b.Y, b.update, b.gains, b.it), saved):
+            t.copy_(v)
+        b.iterate()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.iterate()
+        e1.record()
+        torch.cuda.synchronize()
+        times[S] = e0.elapsed_time(e1) / reps
+    b.close()
+    best = min(times, key=times.get) if times else prev
+    ctx.set_item_points(best)
+    return best, times

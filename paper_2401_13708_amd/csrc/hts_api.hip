@@ -571,6 +571,14 @@ hts_status hts_jobs_schedule(hts_ctx c, hts_stream stream, int32_t n_jobs, int32
     return HTS_OK;
 }
 
+// ---------------------------------------------------------------- tuning
+hts_status hts_set_item_points(hts_ctx c, int32_t item_points) {
+    if (!c) return fail(HTS_EINVAL, "hts_set_item_points: ctx is NULL");
+    if (item_points < 1) return fail(HTS_EINVAL, "hts_set_item_points: item_points must be >= 1");
+    c->item_points = item_points;
+    return HTS_OK;
+}
+
 // ---------------------------------------------------------------- timing
 hts_status hts_timing_enable(hts_ctx c, int32_t on) {
     if (!c) return fail(HTS_EINVAL, "hts_timing_enable: ctx is NULL");

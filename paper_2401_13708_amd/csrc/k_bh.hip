@@ -27,8 +27,6 @@
 // of a query block occupy one contiguous run of the item list, and the
 // combine adds them in emission order, so the result does not depend on
 // scheduling.
-#include <cstdlib>
-
 #include "hts_impl.hpp"
 #include "hts_math.hpp"
 
@@ -468,15 +466,6 @@ __global__ __launch_bounds__(kBlock) void k_bh_finalize(
     grad[2 * (int64_t)i + 1] = oy;
 }
 
-static int item_points() {
-    static int s = [] {
-        int v = 512;
-        if (const char *e = std::getenv("HTS_ITEM_POINTS")) v = std::atoi(e);  // tuning knob
-        return v < 1 ? 1 : v;
-    }();
-    return s;
-}
-
 template <typename T>
 hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, const T *fattr,
                                double ex, const double *ex_job, T *grad, double *z_dev,
@@ -484,7 +473,7 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const int64_t nqb = t->nqb;
     const Jobs jb = jobs_of(t);
     const int64_t slots = nqb * kItemCap;
-    const int S = item_points();
+    const int S = ctx->item_points;
     // workspace: item list, partials, per-block sums
     const size_t b_base = (size_t)nqb * 4, b_nit = (size_t)nqb * 4;
     const size_t b_part0 = (size_t)n * 2 * sizeof(T), b_ztop = (size_t)nqb * 8;

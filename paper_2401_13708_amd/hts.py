@@ -52,6 +52,7 @@ _SIGS = {
                                        _P]),
     "hts_step_jobs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _I32, _P, _P, _D, _D, _I32]),
     "hts_jobs_schedule": (C.c_int, [_P, _P, _I32, _P, _I32, _D, _D, _D, _P, _P]),
+    "hts_set_item_points": (C.c_int, [_P, _I32]),
     "hts_timing_enable": (C.c_int, [_P, _I32]),
     "hts_timing_read": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_I64)]),
 }
@@ -141,6 +142,11 @@ class Context:
         if code not in (0, -5):
             _ck(code)
         return int(bits.value)
+
+    def set_item_points(self, s: int):
+        """Barnes-Hut work-item size (a tuning parameter)."""
+        _ck(lib().hts_set_item_points(self.h, int(s)))
+        self.item_points = int(s)
 
     # ------------------------------------------------------------ timing
     def timing(self, on: bool):

@@ -1,0 +1,224 @@
+"""Continuous-batching server for hyperbolic t-SNE jobs on one GPU.
+
+Requests (a data matrix X and an iteration count) arrive over time.  A
+request waits until its device footprint fits the HBM budget next to the
+running jobs, then is admitted: its affinities P are built on the GPU and it
+joins the running job layout (`batch.JobBatch`), where every iteration
+advances all admitted jobs in the same launches, each at its own point of the
+schedule of Sec. 5.  A job leaves the layout after exactly its iteration
+count; its result is copied to the host at that moment.  P, tree and
+positions stay on the device for the job's whole life.
+
+The layout is rebuilt only when jobs join or leave (state is carried over,
+the tree storage is reused while it is large enough).  Each job's result is
+bit for bit the one it gets alone (`embed.Embedding`), whatever else runs
+beside it.
+
+`FifoServer` is the comparison: the same requests served one at a time with
+the single-job calls.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+import torch
+
+from . import hts
+from .batch import Job, JobBatch
+from .embed import Embedding, Schedule
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the run
+    X: np.ndarray           # n x d data (float32)
+    iters: int = 500
+    seed: int = 0           # of the start embedding (uniform in a disk of radius 1e-4)
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    n: int
+    arrival: float
+    admitted: float
+    finished: float
+    Y: np.ndarray
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def footprint_bytes(n: int, k: int = 90, max_depth: int = 20) -> int:
+    """Device bytes a job of n points holds while it runs: P (at most 2nk
+    entries of column + value, and row pointers), the state and gradient
+    arrays, its share of the tree storage and of the traversal workspace."""
+    p = 2 * n * k * 8 + (n + 1) * 8
+    state = n * 2 * 4 * 4
+    tree = n * (max_depth + 1) * 56 + n * 120
+    trav = (n // 64 + 1) * 256 * (64 * 2 * 4 + 48)
+    return p + state + tree + trav
+
+
+def _start_embedding(n: int, seed: int, dev) -> torch.Tensor:
+    from . import synth
+    return torch.from_numpy(synth.disk_uniform(n, 1e-4, seed=seed)).to(dev)
+
+
+class Server:
+    """Admission by footprint, one running job layout, continuous batching."""
+
+    def __init__(self, ctx: hts.Context, hbm_budget: int, theta: float = 0.5,
+                 perplexity: float = 30.0, k: int = 90, schedule: Schedule | None = None,
+                 max_depth: int = 20):
+        self.ctx, self.budget, self.theta = ctx, int(hbm_budget), theta
+        self.perplexity, self.k = perplexity, k
+        self.sched = schedule or Schedule()
+        self.max_depth = max_depth
+        self.dev = torch.device("cuda", ctx.device)
+        self.max_active = 0
+        self.relayouts = 0
+
+    def _admit(self, req: Request) -> dict:
+        X = torch.from_numpy(np.ascontiguousarray(req.X, dtype=np.float32)).to(self.dev)
+        n = X.shape[0]
+        _, rp, col, val = hts.build_affinities(self.ctx, X, self.perplexity, min(self.k, n - 1),
+                                               p_dtype=torch.float32, want_knn=False)
+        job = Job(rp, col, val, _start_embedding(n, req.seed, self.dev), name=str(req.rid))
+        return {"req": req, "job": job, "done": 0, "admitted": None, "state": None}
+
+    def _layout(self, active, old: JobBatch | None) -> JobBatch | None:
+        tree = old.release_tree() if old is not None else None
+        if not active:
+            if tree is not None:
+                tree.close()
+            return None
+        carry = [a["state"] for a in active]
+        b = JobBatch(self.ctx, [a["job"] for a in active], theta=self.theta,
+                     max_depth=self.max_depth, schedule=self.sched,
+                     start_iter=[a["done"] for a in active], carry=carry, tree=tree)
+        self.relayouts += 1
+        return b
+
+    def run(self, requests: list[Request]) -> list[Result]:
+        pending = sorted(requests, key=lambda r: r.arrival)
+        waiting, active, results = [], [], []
+        batch = None
+        used = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        while pending or waiting or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                waiting.append(pending.pop(0))
+            changed = False
+            # admission in arrival order while the footprint fits (a job
+            # larger than the whole budget runs alone)
+            while waiting:
+                fp = footprint_bytes(waiting[0].X.shape[0], self.k, self.max_depth)
+                if active and used + fp > self.budget:
+                    break
+                req = waiting.pop(0)
+                a = self._admit(req)
+                a["admitted"] = now()
+                a["fp"] = fp
+                used += fp
+                active.append(a)
+                changed = True
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(pending[0].arrival - now(), 0.01)))
+                continue
+            if changed:
+                if batch is not None:
+                    for j, a in enumerate(active[:len(batch.jobs)]):
+                        a["state"] = batch.state(j)
+                batch = self._layout(active, batch)
+                for a in active:
+                    a["state"] = None
+                self.max_active = max(self.max_active, len(active))
+            # iterate until the next job completes or a new request arrives
+            left = min(a["req"].iters - a["done"] for a in active)
+            steps = 0
+            while steps < left:
+                batch.iterate()
+                steps += 1
+                if pending and pending[0].arrival <= now() and steps % 8 == 0:
+                    break
+            for a in active:
+                a["done"] += steps
+            finished = [i for i, a in enumerate(active) if a["done"] >= a["req"].iters]
+            if finished:
+                torch.cuda.synchronize()
+                tf = now()
+                keep = []
+                for i, a in enumerate(active):
+                    if i in finished:
+                        Y = batch.state(i)[0].cpu().numpy()
+                        results.append(Result(a["req"].rid, a["job"].n, a["req"].arrival,
+                                              a["admitted"], tf, Y))
+                        used -= a["fp"]
+                    else:
+                        a["state"] = batch.state(i)
+                        keep.append(a)
+                active = keep
+                batch = self._layout(active, batch)
+                for a in active:
+                    a["state"] = None
+        if batch is not None:
+            batch.close()
+        if self.ctx.check() != 0:
+            raise RuntimeError("device error word set")
+        return results
+
+
+class FifoServer:
+    """The same requests, one job at a time with the single-job calls."""
+
+    def __init__(self, ctx: hts.Context, theta: float = 0.5, perplexity: float = 30.0, k: int = 90,
+                 schedule: Schedule | None = None, max_depth: int = 20):
+        self.ctx, self.theta, self.perplexity, self.k = ctx, theta, perplexity, k
+        self.sched = schedule or Schedule()
+        self.max_depth = max_depth
+        self.dev = torch.device("cuda", ctx.device)
+
+    def run(self, requests: list[Request]) -> list[Result]:
+        results = []
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        for req in sorted(requests, key=lambda r: r.arrival):
+            while now() < req.arrival:
+                time.sleep(min(req.arrival - now(), 0.01))
+            ta = now()
+            X = torch.from_numpy(np.ascontiguousarray(req.X, dtype=np.float32)).to(self.dev)
+            n = X.shape[0]
+            _, rp, col, val = hts.build_affinities(self.ctx, X, self.perplexity, min(self.k, n - 1),
+                                                   p_dtype=torch.float32, want_knn=False)
+            e = Embedding(self.ctx, rp, col, val, _start_embedding(n, req.seed, self.dev),
+                          theta=self.theta, max_depth=self.max_depth, schedule=self.sched)
+            e.run(req.iters)
+            Y = e.Y.cpu().numpy()
+            e.close()
+            results.append(Result(req.rid, n, req.arrival, ta, now(), Y))
+        if self.ctx.check() != 0:
+            raise RuntimeError("device error word set")
+        return results
+
+
+def summarize(results: list[Result], skip: int = 0) -> dict:
+    """jobs/s over the measured window and p50/p99 completion latency,
+    leaving out the first `skip` requests (by id) as warm-up."""
+    rs = sorted(results, key=lambda r: r.rid)[skip:]
+    if not rs:
+        return {}
+    lat = np.array([r.latency for r in rs])
+    t_first = min(r.arrival for r in rs)
+    t_last = max(r.finished for r in rs)
+    return {"jobs": len(rs), "jobs_per_s": len(rs) / max(t_last - t_first, 1e-9),
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean())}
