@@ -59,6 +59,12 @@ def lib():
         L.ora_z_exact.argtypes = [_D, C.c_int64, _D]
         L.ora_tree_build.argtypes = [_D, C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]
         L.ora_tree_build_partition.argtypes = [_D, C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]
+        L.ora_tree_build_rule.argtypes = [_D, C.c_int64, C.c_int32, C.c_int32,
+                                          C.POINTER(C.c_void_p)]
+        L.ora_tree_build_partition_rule.argtypes = [_D, C.c_int64, C.c_int32, C.c_int32,
+                                                    C.POINTER(C.c_void_p)]
+        L.ora_radial_mid.restype = C.c_double
+        L.ora_radial_mid.argtypes = [C.c_double, C.c_double, C.c_int32]
         L.ora_tree_free.argtypes = [C.c_void_p]
         L.ora_tree_num_nodes.restype = C.c_int64
         L.ora_tree_num_nodes.argtypes = [C.c_void_p]
@@ -221,14 +227,20 @@ def gradient_exact_rows(Y, rp, col, val, rows, z: float, exaggeration: float = 1
     return g
 
 
+def radial_mid(lo: float, hi: float, split_rule: int) -> float:
+    """Radial split point of a cell (eq. (10) for rule 0, eq. (9) for rule 1)."""
+    return float(lib().ora_radial_mid(float(lo), float(hi), int(split_rule)))
+
+
 class Tree:
     """Polar quadtree built by insertion (or by recursive partition)."""
 
-    def __init__(self, Y, max_depth: int = 20, method: str = "insert"):
+    def __init__(self, Y, max_depth: int = 20, method: str = "insert", split_rule: int = 0):
         self.Y = _f64(Y).reshape(-1, 2)
         h = C.c_void_p()
-        fn = lib().ora_tree_build if method == "insert" else lib().ora_tree_build_partition
-        _check(fn(_p(self.Y, _D), self.Y.shape[0], max_depth, C.byref(h)), "tree_build")
+        fn = lib().ora_tree_build_rule if method == "insert" else lib().ora_tree_build_partition_rule
+        _check(fn(_p(self.Y, _D), self.Y.shape[0], max_depth, int(split_rule), C.byref(h)),
+               "tree_build")
         self.h = h
         self.n_nodes = int(lib().ora_tree_num_nodes(h))
 

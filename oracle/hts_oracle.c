@@ -458,6 +458,7 @@ typedef struct {
 struct ora_tree {
     int64_t n;
     int32_t max_depth;
+    int32_t split_rule; /* 0: equal radial lengths, eq. (10); 1: equal areas, eq. (9) */
     double *px, *py;   /* point coordinates (full precision) */
     double *r, *phi;   /* polar position of the FP32-rounded coordinates */
     onode *nodes;
@@ -500,21 +501,37 @@ static int32_t new_node(ora_tree *t, double rlo, double rhi, double plo,
     return (int32_t)t->nn++;
 }
 
+/* Radial split point of a cell with embedding radii [lo, hi].
+ * rule 0, eq. (10): the mean of the two radii (equal lengths in the disk).
+ * rule 1, eq. (9): the hyperbolic radius rho = 2 artanh(r) whose cosh is the
+ * mean of cosh(rho_lo) and cosh(rho_hi), so that both halves of the annulus
+ * have the same hyperbolic area (2 pi (cosh rho - 1) inside radius rho).
+ * Written in the embedding radius with cosh(rho) = 1 + 2u, u = r^2/(1-r^2):
+ * the mean of the cosh values is 1 + (u_lo + u_hi), and r^2 = u/(1+u) gives
+ * mid^2 = s / (2 + s) with s = u_lo + u_hi (the same number as the cosh and
+ * acosh form, without their cancellation near r = 0). */
+double ora_radial_mid(double lo, double hi, int32_t rule) {
+    if (rule == 0) return (lo + hi) * 0.5;
+    double ulo = lo * lo / (1.0 - lo * lo);
+    double uhi = hi * hi / (1.0 - hi * hi);
+    double sum = ulo + uhi;
+    return sqrt(sum / (2.0 + sum));
+}
+
 /* Split of a cell into four (Sec. 4-A): the angular range is halved,
- * mid_phi = (max_phi + min_phi) / 2 (Sec. 2-D), and the radial range is
- * halved in embedding radius, mid_r = (max_r + min_r) / 2 (eq. (10)).
- * Children are numbered 2 * [r >= mid_r] + [phi >= mid_phi]. */
-static int digit_of(const onode *o, double r, double phi) {
-    double mr = (o->r_lo + o->r_hi) * 0.5;
+ * mid_phi = (max_phi + min_phi) / 2 (Sec. 2-D), and the radial range at
+ * ora_radial_mid.  Children are numbered 2 * [r >= mid_r] + [phi >= mid_phi]. */
+static int digit_of(const ora_tree *t, const onode *o, double r, double phi) {
+    double mr = ora_radial_mid(o->r_lo, o->r_hi, t->split_rule);
     double mp = (o->p_lo + o->p_hi) * 0.5;
     return 2 * (r >= mr) + (phi >= mp);
 }
 
 static int32_t child_of(ora_tree *t, int32_t nid, int64_t p) {
     onode *o = &t->nodes[nid];
-    int dg = digit_of(o, t->r[p], t->phi[p]);
+    int dg = digit_of(t, o, t->r[p], t->phi[p]);
     if (o->child[dg] >= 0) return o->child[dg];
-    double mr = (o->r_lo + o->r_hi) * 0.5;
+    double mr = ora_radial_mid(o->r_lo, o->r_hi, t->split_rule);
     double mp = (o->p_lo + o->p_hi) * 0.5;
     double rlo = (dg & 2) ? mr : o->r_lo, rhi = (dg & 2) ? o->r_hi : mr;
     double plo = (dg & 1) ? mp : o->p_lo, phi = (dg & 1) ? o->p_hi : mp;
@@ -561,11 +578,12 @@ static int insert_point(ora_tree *t, int32_t nid, int64_t p, int count_here) {
     }
 }
 
-static ora_tree *tree_alloc(const double *Y, int64_t n, int32_t max_depth) {
+static ora_tree *tree_alloc(const double *Y, int64_t n, int32_t max_depth, int32_t rule) {
     ora_tree *t = (ora_tree *)calloc(1, sizeof(ora_tree));
     if (!t) return NULL;
     t->n = n;
     t->max_depth = max_depth;
+    t->split_rule = rule;
     t->px = (double *)malloc(sizeof(double) * (size_t)n);
     t->py = (double *)malloc(sizeof(double) * (size_t)n);
     t->r = (double *)malloc(sizeof(double) * (size_t)n);
@@ -667,8 +685,14 @@ static int finish_tree(ora_tree *t) {
 
 int ora_tree_build(const double *Y, int64_t n, int32_t max_depth,
                    ora_tree **out) {
+    return ora_tree_build_rule(Y, n, max_depth, 0, out);
+}
+
+int ora_tree_build_rule(const double *Y, int64_t n, int32_t max_depth,
+                        int32_t split_rule, ora_tree **out) {
     if (n < 2 || max_depth < 1 || max_depth > 30) return -1;
-    ora_tree *t = tree_alloc(Y, n, max_depth);
+    if (split_rule != 0 && split_rule != 1) return -1;
+    ora_tree *t = tree_alloc(Y, n, max_depth, split_rule);
     if (!t) return -2;
     if (make_root(t) < 0) { ora_tree_free(t); return -2; }
     for (int64_t p = 0; p < n; ++p)
@@ -691,11 +715,11 @@ static int partition(ora_tree *t, int32_t nid, int64_t *idx, int64_t cnt,
     o->is_leaf = 0;
     int64_t start[5] = {0, 0, 0, 0, 0};
     for (int64_t a = 0; a < cnt; ++a)
-        start[digit_of(&t->nodes[nid], t->r[idx[a]], t->phi[idx[a]]) + 1]++;
+        start[digit_of(t, &t->nodes[nid], t->r[idx[a]], t->phi[idx[a]]) + 1]++;
     for (int c = 0; c < 4; ++c) start[c + 1] += start[c];
     int64_t fill[4] = {start[0], start[1], start[2], start[3]};
     for (int64_t a = 0; a < cnt; ++a) {
-        int dg = digit_of(&t->nodes[nid], t->r[idx[a]], t->phi[idx[a]]);
+        int dg = digit_of(t, &t->nodes[nid], t->r[idx[a]], t->phi[idx[a]]);
         tmp[fill[dg]++] = idx[a];
     }
     memcpy(idx, tmp, sizeof(int64_t) * (size_t)cnt);
@@ -711,8 +735,14 @@ static int partition(ora_tree *t, int32_t nid, int64_t *idx, int64_t cnt,
 
 int ora_tree_build_partition(const double *Y, int64_t n, int32_t max_depth,
                              ora_tree **out) {
+    return ora_tree_build_partition_rule(Y, n, max_depth, 0, out);
+}
+
+int ora_tree_build_partition_rule(const double *Y, int64_t n, int32_t max_depth,
+                                  int32_t split_rule, ora_tree **out) {
     if (n < 2 || max_depth < 1 || max_depth > 30) return -1;
-    ora_tree *t = tree_alloc(Y, n, max_depth);
+    if (split_rule != 0 && split_rule != 1) return -1;
+    ora_tree *t = tree_alloc(Y, n, max_depth, split_rule);
     if (!t) return -2;
     int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);

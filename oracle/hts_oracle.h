@@ -62,6 +62,13 @@ int ora_tree_build(const double *Y, int64_t n, int32_t max_depth,
                    ora_tree **out);                       /* by insertion */
 int ora_tree_build_partition(const double *Y, int64_t n, int32_t max_depth,
                              ora_tree **out);             /* by recursive split */
+/* the same with a radial split rule: 0 equal lengths (eq. (10)), 1 equal
+ * hyperbolic areas (eq. (9)) */
+int ora_tree_build_rule(const double *Y, int64_t n, int32_t max_depth,
+                        int32_t split_rule, ora_tree **out);
+int ora_tree_build_partition_rule(const double *Y, int64_t n, int32_t max_depth,
+                                  int32_t split_rule, ora_tree **out);
+double ora_radial_mid(double lo, double hi, int32_t split_rule);
 void ora_tree_free(ora_tree *t);
 int64_t ora_tree_num_nodes(const ora_tree *t);
 /* pre-order export; any pointer may be NULL.  mid is n_nodes x 2, bounds is

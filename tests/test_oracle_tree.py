@@ -175,3 +175,90 @@ def test_midpoints_are_einstein_midpoints_of_cells():
         # the printed form divides by sqrt(1 - |v|^2), which cancels near the rim
         tol = 1e-12 + 1e-16 / np.min(1 - np.sum(pts * pts, 1)) ** 2
         assert np.allclose(e["mid"][k], m, rtol=tol, atol=1e-15)
+
+
+# ---------------------------------------------------------------- eq. (9)
+def test_equal_area_mid_is_the_printed_formula():
+    # eq. (9) in the hyperbolic radius rho = 2 artanh(r), evaluated literally
+    g = np.random.default_rng(7)
+    for lo, hi in [(0.0, 0.5), (0.1, 0.2), (1e-4, 2e-4), (0.9, 0.99999), (0.3, 0.3000001)]:
+        rlo, rhi = 2 * np.arctanh(lo), 2 * np.arctanh(hi)
+        mid_rho = np.arccosh((np.cosh(rhi) + np.cosh(rlo)) / 2)
+        want = np.tanh(mid_rho / 2)
+        assert oracle.radial_mid(lo, hi, 1) == pytest.approx(want, rel=1e-9), (lo, hi)
+    for _ in range(200):
+        lo, hi = np.sort(g.uniform(0, 0.999, 2))
+        rlo, rhi = 2 * np.arctanh(lo), 2 * np.arctanh(hi)
+        want = np.tanh(np.arccosh((np.cosh(rhi) + np.cosh(rlo)) / 2) / 2)
+        assert oracle.radial_mid(lo, hi, 1) == pytest.approx(want, rel=1e-9)
+    assert oracle.radial_mid(0.2, 0.6, 0) == 0.4
+
+
+def test_equal_area_mid_halves_the_hyperbolic_area():
+    # the area inside hyperbolic radius rho is 2 pi (cosh rho - 1), and
+    # cosh rho = (1 + r^2) / (1 - r^2): both halves of the annulus are equal
+    ch = lambda r: (1 + r * r) / (1 - r * r)
+    g = np.random.default_rng(8)
+    for _ in range(200):
+        lo, hi = np.sort(g.uniform(0, 0.99, 2))
+        m = oracle.radial_mid(lo, hi, 1)
+        assert lo <= m <= hi
+        inner, outer = ch(m) - ch(lo), ch(hi) - ch(m)
+        assert inner == pytest.approx(outer, rel=1e-9, abs=1e-15)
+    # the split lies outside the equal-length mid (area grows with the radius)
+    assert oracle.radial_mid(0.0, 0.9, 1) > 0.45
+
+
+@pytest.mark.parametrize("name,Y", _inputs())
+def test_equal_area_insertion_equals_partition(name, Y):
+    a = oracle.Tree(Y, L, "insert", split_rule=1).export()
+    b = oracle.Tree(Y, L, "partition", split_rule=1).export()
+    for key in ("count", "depth", "first", "next", "perm"):
+        assert np.array_equal(a[key], b[key]), key
+    # cells split at the equal-area radius
+    for k in range(a["count"].size):
+        if a["next"][k] != k + 1 and a["depth"][k] < L:
+            rlo, rhi = a["bounds"][k][:2]
+            c = k + 1
+            while c < a["next"][k]:
+                blo, bhi = a["bounds"][c][:2]
+                m = oracle.radial_mid(rlo, rhi, 1)
+                assert (blo, bhi) in ((rlo, m), (m, rhi))
+                c = a["next"][c]
+
+
+def test_equal_area_small_tree_matches_brute_force():
+    Y = synth.disk_state(48, "late", n_clusters=3, seed=9).astype(np.float64)
+    r, p = _polar32(Y)
+    ch = lambda x: (1 + x * x) / (1 - x * x)
+    n, depth = Y.shape[0], 8
+    keys = []
+    for i in range(n):
+        lo, hi, plo, phi = r.min(), r.max(), 0.0, 2 * np.pi
+        dig = []
+        for _ in range(depth):
+            # equal-area split found by bisection on the area balance
+            a, b = lo, hi
+            for _ in range(200):
+                m = 0.5 * (a + b)
+                if ch(m) - ch(lo) < ch(hi) - ch(m):
+                    a = m
+                else:
+                    b = m
+            mr = oracle.radial_mid(lo, hi, 1)
+            assert abs(mr - 0.5 * (a + b)) <= 1e-12 * max(1.0, hi)
+            mp = (plo + phi) * 0.5
+            rb, pb = int(r[i] >= mr), int(p[i] >= mp)
+            dig.append(2 * rb + pb)
+            lo, hi = (mr, hi) if rb else (lo, mr)
+            plo, phi = (mp, phi) if pb else (plo, mp)
+        keys.append(tuple(dig))
+    nodes = {(): n}
+    for lvl in range(1, depth + 1):
+        for i in range(n):
+            parent = keys[i][:lvl - 1]
+            if sum(1 for k in keys if k[:lvl - 1] == parent) >= 2:
+                nodes[keys[i][:lvl]] = sum(1 for k in keys if k[:lvl] == keys[i][:lvl])
+    want = [(len(k), nodes[k]) for k in sorted(nodes)]
+    e = oracle.Tree(Y, depth, split_rule=1).export()
+    assert list(zip(e["depth"].tolist(), e["count"].tolist())) == want
