@@ -265,6 +265,8 @@ def main():
     ap.add_argument("--no-stats", action="store_true", help="time without traversal counters")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for PMC calibration)")
+    ap.add_argument("--split-rule", type=int, choices=[0, 1], default=0,
+                    help="radial split: 0 equal lengths (eq. (10)), 1 equal areas (eq. (9))")
     ap.add_argument("--workload", choices=["single", "jobs", "serve"], default="single",
                     help="single: the N=70k iteration (default); jobs: 64 uneven jobs batched; "
                          "serve: Poisson arrivals through the continuous-batching server")
@@ -315,7 +317,7 @@ def main():
     def run_pass(events, stats):
         """Warm-up + the timed iterations from the same start; the iteration
         is deterministic, so every pass follows the same trajectory."""
-        emb = Embedding(ctx, rp, col, val, Y0d, theta=args.theta)
+        emb = Embedding(ctx, rp, col, val, Y0d, theta=args.theta, split_rule=args.split_rule)
         for _ in range(args.warmup):
             emb.iterate()
         torch.cuda.synchronize()
@@ -442,7 +444,9 @@ def main():
                                "mixture, perplexity 30, k=90, theta=%.2f, iterations %d-%d of the "
                                "1000-iteration schedule" % (n, d, args.theta, args.warmup,
                                                             args.warmup + args.steps - 1),
-                   "n": n, "d": d, "theta": args.theta, "perplexity": 30, "k": 90, "nnz": nnz},
+                   "n": n, "d": d, "theta": args.theta, "perplexity": 30, "k": 90, "nnz": nnz,
+                   "split_rule": "equal lengths, eq. (10)" if args.split_rule == 0
+                   else "equal areas, eq. (9)"},
         "exact_iters_per_s": round(exact_ips, 3) if exact_ips else None,
         "speedup_vs_exact": round(value / exact_ips, 1) if exact_ips else None,
         "kernel_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kt.items() if v[1]},

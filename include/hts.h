@@ -122,6 +122,13 @@ hts_status hts_tree_destroy(hts_tree tree);
 hts_status hts_tree_set_jobs(hts_tree tree, int32_t n_jobs,
                              const int64_t *n_per_job);
 
+/* Radial split rule of later builds (Sec. 2-D, Sec. 4-A): 0 (default) splits
+ * a cell's radial range at the mean embedding radius, eq. (10); 1 splits it
+ * into two parts of equal hyperbolic area, eq. (9) (mid^2 = s / (2 + s) with
+ * s = lo^2/(1-lo^2) + hi^2/(1-hi^2), the same point written in the embedding
+ * radius).  The angular split is the same for both. */
+hts_status hts_tree_set_split(hts_tree tree, int32_t split_rule);
+
 /* Builds the tree of Y (n points, 2 <= n <= n_max) on the stream (one tree
  * per job of the layout).  The tree keeps its own copy of everything it
  * needs; Y may change afterwards. */

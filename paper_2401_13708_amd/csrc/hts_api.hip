@@ -305,6 +305,15 @@ hts_status hts_tree_set_jobs(hts_tree t, int32_t n_jobs, const int64_t *n_per_jo
     return HTS_OK;
 }
 
+hts_status hts_tree_set_split(hts_tree t, int32_t split_rule) {
+    if (!t) return fail(HTS_EINVAL, "hts_tree_set_split: tree is NULL");
+    if (split_rule != 0 && split_rule != 1)
+        return fail(HTS_EINVAL, "hts_tree_set_split: split_rule must be 0 or 1");
+    t->split_rule = split_rule;
+    t->n = 0;  // rebuild before the next traversal
+    return HTS_OK;
+}
+
 hts_status hts_build_polar_tree(hts_ctx c, hts_stream stream, const void *Y, int64_t n,
                                 int32_t y_dtype, hts_tree t) {
     if (!c || !t) return fail(HTS_EINVAL, "hts_build_polar_tree: NULL handle");

@@ -131,6 +131,7 @@ struct hts_tree_s {
     int32_t *node_first = nullptr; // [cap_nodes]
     double *sinhalf = nullptr;     // [32] sin(pi / 2^l), 1 for l <= 1
     int32_t job_bits = 0;          // key bits above the 2 max_depth cell bits
+    int32_t split_rule = 0;        // 0: equal radial lengths (eq. (10)); 1: equal areas (eq. (9))
 };
 
 namespace hts {

@@ -4,7 +4,8 @@
 //  1. polar position of every point (double, from the single-precision
 //     coordinates) and per-block min/max of r;
 //  2. key of every point: max_depth levels of the split rule, two bits per
-//     level (radial bit: r >= (lo + hi) / 2 of eq. (10); angular bit:
+//     level (radial bit: r at or above the radial split of eq. (10), or of
+//     eq. (9) when the tree is set to equal areas; angular bit:
 //     phi >= (lo + hi) / 2), most significant level first;
 //  3. stable radix sort of (key, index);
 //  4. per sorted position: how many nodes start there (from the common
@@ -119,6 +120,21 @@ __global__ __launch_bounds__(kBlock) void k_root(const int64_t *__restrict__ job
     }
 }
 
+// Radial split point of a cell with embedding radii [lo, hi]: rule 0 halves
+// the radial length (eq. (10)); rule 1 splits at the hyperbolic radius whose
+// cosh is the mean of the two bounds' (eq. (9), equal hyperbolic areas),
+// computed in the embedding radius through cosh(rho) = 1 + 2 r^2 / (1 - r^2):
+// mid^2 = s / (2 + s), s = lo^2/(1-lo^2) + hi^2/(1-hi^2).  Every operation
+// is rounded on its own (no fused multiply-add), so the split points are
+// reproducible to the bit.
+__device__ __forceinline__ double radial_mid(double lo, double hi, int rule) {
+#pragma clang fp contract(off)
+    if (rule == 0) return __dmul_rn(__dadd_rn(lo, hi), 0.5);
+    const double l2 = __dmul_rn(lo, lo), h2 = __dmul_rn(hi, hi);
+    const double s = __dadd_rn(__ddiv_rn(l2, __dsub_rn(1.0, l2)), __ddiv_rn(h2, __dsub_rn(1.0, h2)));
+    return __dsqrt_rn(__ddiv_rn(s, __dadd_rn(2.0, s)));
+}
+
 // ---------------------------------------------------------------- 2. keys
 // job index above max_depth levels of the split rule, two bits per level
 // (radial bit: r >= (lo + hi) / 2 of eq. (10); angular bit: phi >= (lo + hi) / 2)
@@ -126,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
                                                  const double *__restrict__ phi, int64_t n,
                                                  const int32_t *__restrict__ pjob,
                                                  const double *__restrict__ root, int L,
-                                                 uint64_t *__restrict__ keys,
+                                                 int split, uint64_t *__restrict__ keys,
                                                  uint32_t *__restrict__ idx) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -135,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
     double lo = root[2 * job], hi = root[2 * job + 1], plo = 0.0, phh = kTwoPi;
     uint64_t key = (uint64_t)job;
     for (int l = 0; l < L; ++l) {
-        double mr = __dmul_rn(__dadd_rn(lo, hi), 0.5);
+        double mr = radial_mid(lo, hi, split);
         double mp = __dmul_rn(__dadd_rn(plo, phh), 0.5);
         int rb = rv >= mr, pb = pv >= mp;
         key = (key << 2) | (uint64_t)(2 * rb + pb);
@@ -350,7 +366,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
                                                  NodeRec<T> *__restrict__ nodes,
                                                  double *__restrict__ r_cell,
                                                  int32_t *__restrict__ node_first,
-                                                 int64_t cap, uint32_t *__restrict__ err) {
+                                                 int64_t cap, uint32_t *__restrict__ err,
+                                                 int split) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     NodeSpan sp = node_span(keys, i, n, L);
@@ -397,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
         // radial bounds of the cell (same arithmetic as the keys)
         while (lev < l) {
             int rb = (int)((key >> (2 * (L - 1 - lev) + 1)) & 1u);
-            double mr = __dmul_rn(__dadd_rn(lo, hi), 0.5);
+            double mr = radial_mid(lo, hi, split);
             if (rb) lo = mr; else hi = mr;
             ++lev;
         }
@@ -467,7 +484,7 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
                        t->J, t->mm, t->root);
     HTS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kBlock), 0, st, t->r, t->phi, n, t->pjob, t->root, L,
-                       t->keys_in, t->idx_in);
+                       t->split_rule, t->keys_in, t->idx_in);
     HTS_HIP(hipGetLastError());
     size_t bytes = t->sort_tmp_bytes;
     HTS_HIP(rocprim::radix_sort_pairs(t->sort_tmp, bytes, t->keys_in, t->keys, t->idx_in, t->perm,
@@ -484,7 +501,7 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     hipLaunchKernelGGL(k_emit<T>, dim3(nb), dim3(kBlock), 0, st, t->keys, n, L,
                        (const PointRec<T> *)t->spts, t->node_start, t->psum, t->root, t->sinhalf,
                        (NodeRec<T> *)t->nodes, t->r_cell, t->node_first, t->cap_nodes,
-                       ctx->d_err);
+                       ctx->d_err, t->split_rule);
     HTS_HIP(hipGetLastError());
     t->n = n;
     t->dtype = sizeof(T) == 8 ? HTS_F64 : HTS_F32;

@@ -41,7 +41,8 @@ class Embedding:
     """Device-resident state (Y, update, gains, P, tree) of one job."""
 
     def __init__(self, ctx: hts.Context, row_ptr, col_idx, p_val, Y0, theta: float = 0.5,
-                 exact: bool = False, max_depth: int = 20, schedule: Schedule | None = None):
+                 exact: bool = False, max_depth: int = 20, schedule: Schedule | None = None,
+                 split_rule: int = 0):
         self.ctx = ctx
         self.rp, self.col, self.val = row_ptr, col_idx, p_val
         self.Y = Y0.clone()
@@ -54,6 +55,8 @@ class Embedding:
         self.exact = exact
         self.sched = schedule or Schedule()
         self.tree = None if exact else hts.Tree(ctx, self.n, max_depth)
+        if self.tree is not None and split_rule:
+            self.tree.set_split(split_rule)
         self.it = 0
 
     def iterate(self, stats=None):

@@ -53,6 +53,7 @@ _SIGS = {
     "hts_step_jobs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _I32, _P, _P, _D, _D, _I32]),
     "hts_jobs_schedule": (C.c_int, [_P, _P, _I32, _P, _I32, _D, _D, _D, _P, _P]),
     "hts_set_item_points": (C.c_int, [_P, _I32]),
+    "hts_tree_set_split": (C.c_int, [_P, _I32]),
     "hts_timing_enable": (C.c_int, [_P, _I32]),
     "hts_timing_read": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_I64)]),
 }
@@ -169,6 +170,11 @@ class Tree:
         self.ctx = ctx
         self.n_max = n_max
         self.max_depth = max_depth
+
+    def set_split(self, rule: int):
+        """Radial split: 0 equal lengths (eq. (10)), 1 equal areas (eq. (9))."""
+        _ck(lib().hts_tree_set_split(self.h, int(rule)))
+        self.split_rule = int(rule)
 
     def set_jobs(self, sizes):
         """Job layout: len(sizes) embeddings of these sizes, side by side."""

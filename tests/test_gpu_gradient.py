@@ -28,9 +28,11 @@ def _run_exact(ctx, Y, rp, col, val, ex):
     return g.cpu().numpy(), float(z.cpu()[0])
 
 
-def _run_bh(ctx, Y, rp, col, val, ex, theta, max_depth=20, stats=False):
+def _run_bh(ctx, Y, rp, col, val, ex, theta, max_depth=20, stats=False, split=0):
     Yd = _dev(Y)
     tree = hts.Tree(ctx, Y.shape[0], max_depth)
+    if split:
+        tree.set_split(split)
     hts.build_polar_tree(ctx, Yd, tree)
     st = torch.zeros(10, dtype=torch.int64, device="cuda") if stats else None
     g, z = hts.gradient_bh(ctx, Yd, _dev(rp), _dev(col), _dev(val), tree, theta, ex, stats=st)
@@ -144,3 +146,15 @@ def test_bh_is_deterministic(ctx):
     a = _run_bh(ctx, Y, rp, col, val.astype(np.float32), 1.0, 0.5)
     b = _run_bh(ctx, Y, rp, col, val.astype(np.float32), 1.0, 0.5)
     assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+@pytest.mark.parametrize("stage", STAGES)
+def test_bh_equal_area_matches_oracle_bh(ctx, stage):
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, stage, np.float64)
+    g, z, st = _run_bh(ctx, Y, rp, col, val, 12.0, 0.5, stats=True, split=1)
+    t = oracle.Tree(Y, split_rule=1)
+    go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 12.0)
+    assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    assert rel(g, go) < 1e-10
+    assert z == pytest.approx(zo, rel=1e-10)

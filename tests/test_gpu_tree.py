@@ -12,17 +12,19 @@ from gpu_inputs import STAGES, embedding
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_tree(ctx, Y, max_depth=20):
+def _gpu_tree(ctx, Y, max_depth=20, split=0):
     t = hts.Tree(ctx, Y.shape[0], max_depth)
+    if split:
+        t.set_split(split)
     hts.build_polar_tree(ctx, torch.from_numpy(Y).cuda(), t)
     out = hts.tree_export(ctx, t, Y.shape[0])
     t.close()
     return out
 
 
-def _compare(ctx, Y, max_depth=20, mid_rtol=1e-12):
-    g = _gpu_tree(ctx, Y, max_depth)
-    o = oracle.Tree(Y.astype(np.float64), max_depth).export()
+def _compare(ctx, Y, max_depth=20, mid_rtol=1e-12, split=0):
+    g = _gpu_tree(ctx, Y, max_depth, split)
+    o = oracle.Tree(Y.astype(np.float64), max_depth, split_rule=split).export()
     assert g["count"].size == o["count"].size
     for key in ("count", "depth", "first", "next"):
         assert np.array_equal(g[key], o[key]), key
@@ -76,3 +78,19 @@ def test_tree_same_radius_and_axis_points(ctx):
     ring = np.stack([0.5 * np.cos(k * 2 * np.pi / 512), 0.5 * np.sin(k * 2 * np.pi / 512)], 1)
     axis = np.array([[0.3, 0.0], [-0.3, 0.0], [0.0, 0.3], [0.0, -0.3], [0.0, 0.0], [1e-30, -1e-30]])
     _compare(ctx, np.concatenate([ring, axis]).astype(np.float64), mid_rtol=1e-11)
+
+
+@pytest.mark.parametrize("stage", STAGES)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_tree_equal_area_split(ctx, stage, dtype):
+    # eq. (9): the split radius is reproduced to the bit, so the node set is
+    # the oracle's
+    _compare(ctx, embedding(4099, stage, dtype), mid_rtol=1.2e-7 if dtype == np.float32 else 1e-11,
+             split=1)
+
+
+def test_tree_equal_area_duplicates_and_caps(ctx):
+    Y = embedding(3000, "late", np.float64)
+    Y[100:160] = Y[7]
+    for depth in (20, 5):
+        _compare(ctx, Y, depth, mid_rtol=1e-11, split=1)
