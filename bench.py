@@ -395,7 +395,7 @@ def main():
     # roofline of the dominant kernel of the timed region
     launches = {k: v[1] for k, v in kt.items()}
     kms = {k: v[0] for k, v in kt.items()}
-    names = {"tree": "tree build (6 kernels)", "attract": "k_attract", "traverse": "k_bh_top",
+    names = {"tree": "tree build (7 kernels)", "attract": "k_attract", "traverse": "k_bh_top (with the attractive rows)",
              "items": "k_bh_items", "finalize": "k_bh_gather + k_bh_finalize", "step": "k_step"}
     dom = max(names, key=lambda k: kms.get(k, 0.0))
     roof = None

@@ -443,9 +443,8 @@ static hts_status bh_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, cons
     PointRec<T> *pts = (PointRec<T> *)c->pts.p;
     HTS_OKR(tree_thresholds(c, st, t, sizeof(T) == 8 ? HTS_F64 : HTS_F32, theta));
     HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
-    HTS_OKR(launch_attract<T>(c, st, pts, rp, col, val, n, (T *)c->fattr.p));
-    return launch_bh_repulsion<T>(c, st, t, n, (const T *)c->fattr.p, ex, ex_job, grad, z_dev,
-                                  stats);
+    return launch_bh_repulsion<T>(c, st, t, n, pts, rp, col, val, (T *)c->fattr.p, ex, ex_job,
+                                  grad, z_dev, stats);
 }
 
 static hts_status bh_tree_args(const char *fn, hts_ctx c, hts_tree t, int64_t n, int32_t dtype,

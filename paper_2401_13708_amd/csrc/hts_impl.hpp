@@ -189,10 +189,12 @@ hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, c
 // Barnes-Hut repulsion over the tree and the combine g = 4 (a F_attr - F_rep / Z)
 // ex_job: per-job exaggeration (device, [J]) or NULL for ex; z_dev receives
 // Z of every job ([J])
+// (the first launch also computes the attractive term into fattr)
 template <typename T>
-hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, const T *fattr,
-                               double ex, const double *ex_job, T *grad, double *z_dev,
-                               uint64_t *stats);
+hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n,
+                               const PointRec<T> *pts, const int64_t *rp, const int32_t *col,
+                               const T *val, T *fattr, double ex, const double *ex_job, T *grad,
+                               double *z_dev, uint64_t *stats);
 
 template <typename T>
 hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,

@@ -137,4 +137,47 @@ __device__ __forceinline__ DD3 dd_zero() {
     return r;
 }
 
+// ---------------------------------------------------------------- attraction
+// First sum of eq. (15) for the rows of one workgroup of kBlock threads:
+// F_attr,i = sum_{j in row i} p_ij w_ij d_ij dd_ij/dy_i.  G lanes share a CSR
+// row; column/value reads are contiguous per row, the point records of the
+// columns are gathered (they stay in L2).
+template <typename T, int G>
+__device__ __forceinline__ void attract_rows(int64_t block, const PointRec<T> *__restrict__ pts,
+                                             const int64_t *__restrict__ rp,
+                                             const int32_t *__restrict__ col,
+                                             const T *__restrict__ val, int64_t n,
+                                             T *__restrict__ fattr, uint32_t *__restrict__ err) {
+    const int64_t gid = block * kBlock + threadIdx.x;
+    const int64_t row = gid / G;
+    const int sub = (int)(gid % G);
+    T fx = 0, fy = 0;
+    if (row < n) {
+        const PointRec<T> q = pts[row];
+        const int64_t e1 = rp[row + 1];
+        for (int64_t e = rp[row] + sub; e < e1; e += G) {
+            const int32_t j = col[e];
+            const T p = val[e];
+            if ((uint32_t)j >= (uint64_t)n) {  // malformed CSR: flag it, never read outside
+                atomicOr(err, HTS_ERR_BAD_INDEX);
+                continue;
+            }
+            const PointRec<T> o = pts[j];
+            double dd;
+            const double t = dist_arg<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, dd);
+            const PairTerm<T> r = pair_term<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, t, dd);
+            const T coef = (j == row) ? (T)0 : p * r.w * r.base;
+            fx += coef * r.vx;
+            fy += coef * r.vy;
+        }
+    }
+    fx = group_sum<G>(fx);
+    fy = group_sum<G>(fy);
+    if (row < n && sub == 0) {
+        fattr[2 * row] = fx;
+        fattr[2 * row + 1] = fy;
+    }
+}
+
+
 }  // namespace hts

@@ -10,19 +10,19 @@
 // set of lanes that need the children.  Leaves are evaluated exactly, skipping
 // the query.  The lanes that need a subtree form a 64-bit mask per depth, kept
 // in two VGPRs used as lane-indexed arrays (readlane with the depth to read,
-// a lane select to write).  Node records are read from a window of 64
-// consecutive pre-order records held one per lane (one coalesced load, then
-// readlane), so a subtree of up to 64 nodes is walked without memory traffic.
+// a lane select to write).  Node records are read with scalar loads, both
+// possible successors (first child, next sibling) in flight while a node is
+// evaluated; enough waves per SIMD hide their latency.
 //
 // One wave walking the whole tree for its block is a long serial chain, so the
 // walk is split in two phases:
 //  A. one wave per query block walks the nodes that hold more than S points;
 //     when some lanes reject a smaller cell, the cell and their mask become a
 //     work item instead of being descended;
-//  B. persistent waves walk the work items, each a short independent chain;
-//     an item record is self-contained (subtree, lane mask, query block), and
-//     a wave fetches the query points and first node window of its next item
-//     while it walks the current one.
+//  B. waves walk the work items, each a short independent chain; an item
+//     record is self-contained (subtree, lane mask, query block).  The grid
+//     holds several times the waves that fit on the chip, so the hardware
+//     hands the next waves (and their items) to whichever SIMD frees up.
 // Every item writes its own partial force per lane and partial Z; the items
 // of a query block occupy one contiguous run of the item list, and the
 // combine adds them in emission order, so the result does not depend on
@@ -33,6 +33,7 @@
 namespace hts {
 
 constexpr int kStats = 5;
+constexpr int kAttractLanes = 16;  // lanes per CSR row of the attractive term
 constexpr int kItemCap = 256;  // items one query block can hand to phase B
 
 // work item as phase A records it (in LDS) ...
@@ -65,79 +66,31 @@ __device__ __forceinline__ void add_term(const PointRec<T> &me, T ox, T oy, doub
     z += (double)(weight * r.w);
 }
 
-// 64 consecutive node records, record wbase + r held by lane r
-template <typename T>
-struct Window {
-    uint4 v[sizeof(NodeRec<T>) / 16];
-};
-
-template <typename T>
-__device__ __forceinline__ void window_load(Window<T> &win, const NodeRec<T> *__restrict__ nodes,
-                                            int base, int M, int lane) {
-    int idx = base + lane;
-    if (idx >= M) idx = M - 1;
-    const uint4 *src = reinterpret_cast<const uint4 *>(nodes + idx);
-#pragma unroll
-    for (int j = 0; j < (int)(sizeof(NodeRec<T>) / 16); ++j) win.v[j] = src[j];
-}
-
-template <typename T>
-__device__ __forceinline__ NodeRec<T> window_get(const Window<T> &win, int r) {
-    uint32_t d[sizeof(NodeRec<T>) / 4];
-#pragma unroll
-    for (int j = 0; j < (int)(sizeof(NodeRec<T>) / 16); ++j) {
-        d[4 * j + 0] = (uint32_t)__builtin_amdgcn_readlane((int)win.v[j].x, r);
-        d[4 * j + 1] = (uint32_t)__builtin_amdgcn_readlane((int)win.v[j].y, r);
-        d[4 * j + 2] = (uint32_t)__builtin_amdgcn_readlane((int)win.v[j].z, r);
-        d[4 * j + 3] = (uint32_t)__builtin_amdgcn_readlane((int)win.v[j].w, r);
-    }
-    NodeRec<T> rec;
-    __builtin_memcpy(&rec, d, sizeof(rec));
-    return rec;
-}
-
 // Depth-first walk of the pre-order range [k, kend), which starts at a node
 // of depth d0 and holds its subtree, for the lanes in mask0.  With EMIT, an
 // internal node of at most S points that some lanes reject is appended to the
 // block's item list (while there is room) instead of being descended.
-// In WIN mode, win holds the records from k on.
-template <typename T, bool STATS, bool EMIT, bool WIN>
+// Node records are read with scalar loads (the node index is uniform);
+// both possible successors are fetched while a node is evaluated.
+template <typename T, bool STATS, bool EMIT>
 __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M,
                                      const PointRec<T> *__restrict__ spts, const PointRec<T> &me,
                                      int64_t q, int lane, int k, int kend, int d0, uint64_t mask0,
-                                     int S, LdsItem *items, int &nitems, Window<T> win, T &fx,
-                                     T &fy, double &z, Counters &c) {
+                                     int S, LdsItem *items, int &nitems, T &fx, T &fy, double &z,
+                                     Counters &c) {
     int mlo = lane == d0 ? (int)(uint32_t)mask0 : 0;
     int mhi = lane == d0 ? (int)(uint32_t)(mask0 >> 32) : 0;
-    int wbase = k;
-    NodeRec<T> nrec;
-    if (!WIN) nrec = nodes[k < M ? k : M - 1];
+    NodeRec<T> nrec = nodes[k < M ? k : M - 1];
     while (k < kend) {
-        NodeRec<T> cur;
-        if (WIN) {
-            // small contiguous subtrees: records from the register window
-            if (k - wbase >= kWave) {
-                wbase = k;
-                window_load<T>(win, nodes, wbase, M, lane);
-            }
-            cur = window_get<T>(win, k - wbase);
-        } else {
-            // sparse walks near the root: scalar loads, which hit the scalar
-            // cache for the shared top levels; both possible successors are
-            // fetched while this node is evaluated
-            cur = nrec;
-        }
+        const NodeRec<T> cur = nrec;
         const uint32_t nxd = (uint32_t)uniform((int)cur.next_depth);
         const int next = (int)(nxd & kNextMask);
         const int depth = (int)(nxd >> kNextBits);
         const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
         const bool in = (m >> lane) & 1ull;
-        NodeRec<T> down, over;
-        if (!WIN) {
-            down = nodes[k + 1 < M ? k + 1 : k];
-            over = nodes[next < M ? next : k];
-        }
+        const NodeRec<T> down = nodes[k + 1 < M ? k + 1 : k];
+        const NodeRec<T> over = nodes[next < M ? next : k];
         if (STATS) c.step += 1;
         if (next == k + 1) {
             // leaf: exact terms with each of its points, skipping the query
@@ -168,7 +121,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 }
             }
             k = next;
-            if (!WIN) nrec = over;
+            nrec = over;
         } else {
             bool acc = false;
             if (in) {
@@ -188,16 +141,16 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 if (lane == 0) items[nitems] = LdsItem{k, nxd, rej};
                 ++nitems;
                 k = next;
-                if (!WIN) nrec = over;
+                nrec = over;
             } else if (rej) {
                 const bool here = lane == depth + 1;
                 mlo = here ? (int)(uint32_t)rej : mlo;
                 mhi = here ? (int)(uint32_t)(rej >> 32) : mhi;
                 k = k + 1;
-                if (!WIN) nrec = down;
+                nrec = down;
             } else {
                 k = next;
-                if (!WIN) nrec = over;
+                nrec = over;
             }
         }
     }
@@ -214,14 +167,25 @@ __device__ __forceinline__ void put_stats(uint32_t *__restrict__ sp, const Count
 }
 
 // Phase A: one wave per query block over the nodes of more than S points.
+// These few waves are latency-bound and leave most of the chip idle, so the
+// same launch also carries the attractive term (first sum of eq. (15)), which
+// streams P: workgroups from top_blocks on compute its rows.
 template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_top(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
     const int32_t *__restrict__ node_start, Jobs jb, const PointRec<T> *__restrict__ spts,
     int64_t nqb, int S, int *__restrict__ item_base, int *__restrict__ nitems_out,
     T *__restrict__ part0, double *__restrict__ ztop, uint32_t *__restrict__ stats_top,
-    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense) {
+    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense, int64_t top_blocks,
+    const PointRec<T> *__restrict__ pts, const int64_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const T *__restrict__ val, int64_t n, T *__restrict__ fattr,
+    uint32_t *__restrict__ err) {
     __shared__ LdsItem s_items[kBlock / kWave][kItemCap];
+    if ((int64_t)blockIdx.x >= top_blocks) {
+        attract_rows<T, kAttractLanes>((int64_t)blockIdx.x - top_blocks, pts, rp, col, val, n,
+                                       fattr, err);
+        return;
+    }
     const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (qb >= nqb) return;
     const int lane = (int)(threadIdx.x & (kWave - 1));
@@ -243,8 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     double z = 0.0;
     Counters c;
     int nitems = 0;
-    walk<T, STATS, true, false>(nodes, M, spts, me, q, lane, k0, k1, 0, __ballot(valid), S, items,
-                                nitems, Window<T>{}, fx, fy, z, c);
+    walk<T, STATS, true>(nodes, M, spts, me, q, lane, k0, k1, 0, __ballot(valid), S, items,
+                          nitems, fx, fy, z, c);
     // reserve a contiguous run of the item list (one atomic per block; the
     // runs of different blocks may come in any order)
     int base = 0;
@@ -290,10 +254,7 @@ __device__ __forceinline__ ItemRec load_item(const ItemRec *__restrict__ dense, 
     return u;
 }
 
-// Phase B: persistent waves over the item list.  Item i is walked by wave
-// i mod G; while it is walked, the wave already holds the record of item
-// i + G and has the query points and first node window of that item in
-// flight, and the record of item i + 2G is being fetched.
+// Phase B: wave w walks items w, w + G, ... of the item list.
 template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_items(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
@@ -304,36 +265,18 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
     const int M = uniform(*d_m);
     const int64_t total = (int64_t)uniform((int)*dense_count);
     const int64_t G = (int64_t)gridDim.x * (kBlock / kWave);
-    int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (i >= total) return;
     int dummy = 0;
-    ItemRec rec = load_item(dense, i);
-    PointRec<T> me = spts[lane < rec.cnt ? rec.q0 + lane : rec.q0];
-    Window<T> win;
-    window_load<T>(win, nodes, rec.node + 1, M, lane);
-    ItemRec nrec = rec;
-    if (i + G < total) nrec = load_item(dense, i + G);
-    for (;;) {
-        const int64_t i1 = i + G, i2 = i + 2 * G;
-        // next item: query points and first window (its record is here)
-        PointRec<T> nme = me;
-        Window<T> nwin = win;
-        if (i1 < total) {
-            nme = spts[lane < nrec.cnt ? nrec.q0 + lane : nrec.q0];
-            window_load<T>(nwin, nodes, nrec.node + 1, M, lane);
-        }
-        ItemRec nnrec = nrec;
-        if (i2 < total) nnrec = load_item(dense, i2);
-
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < total; i += G) {
+        const ItemRec rec = load_item(dense, i);
+        const PointRec<T> me = spts[lane < rec.cnt ? rec.q0 + lane : rec.q0];
         const int64_t q = (int64_t)rec.q0 + lane;
         const bool valid = lane < rec.cnt;
         T fx = 0, fy = 0;
         double z = 0.0;
         Counters c;
-        // the item's lanes rejected its node in phase A: start at its children
-        walk<T, STATS, false, true>(nodes, M, spts, me, q, lane, rec.node + 1,
-                                    (int)(rec.nd & kNextMask), (int)(rec.nd >> kNextBits) + 1,
-                                    rec.mask, 0, nullptr, dummy, win, fx, fy, z, c);
+        walk<T, STATS, false>(nodes, M, spts, me, q, lane, rec.node + 1,
+                              (int)(rec.nd & kNextMask), (int)(rec.nd >> kNextBits) + 1, rec.mask,
+                              0, nullptr, dummy, fx, fy, z, c);
         if (valid) {
             T *o = part + (i * kWave + lane) * 2;
             o[0] = fx;
@@ -344,12 +287,6 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
             zitem[i] = zs;
             put_stats<STATS>(stats_items + i * kStats, c);
         }
-        if (i1 >= total) break;
-        i = i1;
-        rec = nrec;
-        nrec = nnrec;
-        me = nme;
-        win = nwin;
     }
 }
 
@@ -467,9 +404,10 @@ __global__ __launch_bounds__(kBlock) void k_bh_finalize(
 }
 
 template <typename T>
-hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n, const T *fattr,
-                               double ex, const double *ex_job, T *grad, double *z_dev,
-                               uint64_t *stats) {
+hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n,
+                               const PointRec<T> *pts, const int64_t *rp, const int32_t *col,
+                               const T *val, T *fattr, double ex, const double *ex_job, T *grad,
+                               double *z_dev, uint64_t *stats) {
     const int64_t nqb = t->nqb;
     const Jobs jb = jobs_of(t);
     const int64_t slots = nqb * kItemCap;
@@ -510,18 +448,22 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const PointRec<T> *spts = (const PointRec<T> *)t->spts;
     const dim3 gq(cdiv(nqb, kBlock / kWave));
     int64_t gi = cdiv(slots, kBlock / kWave);
-    if (gi > 256 * 8) gi = 256 * 8;  // persistent: enough waves to fill the chip
+    if (gi > 16384) gi = 16384;  // several waves per SIMD slot: the hardware balances the load
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kWave), 0, st, dense_count);
     {
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
+        const int64_t top_blocks = gq.x;
+        const dim3 ga(top_blocks + cdiv(n * kAttractLanes, kBlock));
         if (stats)
-            hipLaunchKernelGGL((k_bh_top<T, true>), gq, dim3(kBlock), 0, st, nodes, t->d_m,
+            hipLaunchKernelGGL((k_bh_top<T, true>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
-                               st_top, dense_count, dense);
+                               st_top, dense_count, dense, top_blocks, pts, rp, col, val, n, fattr,
+                               ctx->d_err);
         else
-            hipLaunchKernelGGL((k_bh_top<T, false>), gq, dim3(kBlock), 0, st, nodes, t->d_m,
+            hipLaunchKernelGGL((k_bh_top<T, false>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
-                               nullptr, dense_count, dense);
+                               nullptr, dense_count, dense, top_blocks, pts, rp, col, val, n,
+                               fattr, ctx->d_err);
     }
     {
         TimedScope ts(ctx, st, HTS_K_ITEMS);
@@ -549,10 +491,12 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
 }
 
 template hts_status launch_bh_repulsion<float>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                               const float *, double, const double *, float *,
-                                               double *, uint64_t *);
+                                               const PointRec<float> *, const int64_t *,
+                                               const int32_t *, const float *, float *, double,
+                                               const double *, float *, double *, uint64_t *);
 template hts_status launch_bh_repulsion<double>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                                const double *, double, const double *, double *,
-                                                double *, uint64_t *);
+                                                const PointRec<double> *, const int64_t *,
+                                                const int32_t *, const double *, double *, double,
+                                                const double *, double *, double *, uint64_t *);
 
 }  // namespace hts

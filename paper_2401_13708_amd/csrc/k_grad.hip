@@ -34,9 +34,8 @@ hts_status launch_prep_points(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n
 }
 
 // ---------------------------------------------------------------- attraction
-// First sum of eq. (15): F_attr,i = sum_{j in row i} p_ij w_ij d_ij dd_ij/dy_i.
-// G lanes share a CSR row; column/value reads are contiguous per row, the
-// point records of the columns are gathered (they stay in L2).
+// First sum of eq. (15) on its own (the exact path; the Barnes-Hut path runs
+// the same rows inside the first traversal launch).
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_attract(const PointRec<T> *__restrict__ pts,
                                                     const int64_t *__restrict__ rp,
@@ -44,35 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_attract(const PointRec<T> *__restric
                                                     const T *__restrict__ val, int64_t n,
                                                     T *__restrict__ fattr,
                                                     uint32_t *__restrict__ err) {
-    int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int64_t row = gid / G;
-    int sub = (int)(gid % G);
-    T fx = 0, fy = 0;
-    if (row < n) {
-        PointRec<T> q = pts[row];
-        int64_t e1 = rp[row + 1];
-        for (int64_t e = rp[row] + sub; e < e1; e += G) {
-            int32_t j = col[e];
-            T p = val[e];
-            if ((uint32_t)j >= (uint64_t)n) {  // malformed CSR: flag it, never read outside
-                atomicOr(err, HTS_ERR_BAD_INDEX);
-                continue;
-            }
-            PointRec<T> o = pts[j];
-            double dd;
-            double t = dist_arg<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, dd);
-            PairTerm<T> r = pair_term<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, t, dd);
-            T coef = (j == row) ? (T)0 : p * r.w * r.base;
-            fx += coef * r.vx;
-            fy += coef * r.vy;
-        }
-    }
-    fx = group_sum<G>(fx);
-    fy = group_sum<G>(fy);
-    if (row < n && sub == 0) {
-        fattr[2 * row] = fx;
-        fattr[2 * row + 1] = fy;
-    }
+    attract_rows<T, G>(blockIdx.x, pts, rp, col, val, n, fattr, err);
 }
 
 template <typename T>
