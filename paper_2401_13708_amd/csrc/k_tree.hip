@@ -343,15 +343,28 @@ __device__ __forceinline__ double dd_diff(const DD3 &a, const DD3 &b, int c) {
 }
 
 // first position j > i whose key differs from keys[i] in the first l levels
+// (a cell is a contiguous range of the sorted keys): gallop from i with
+// doubling steps, then bisect, so a cell of c points costs about 2 log2(c)
+// loads rather than log2(n)
 __device__ __forceinline__ int64_t cell_end(const uint64_t *__restrict__ keys, int64_t i, int64_t n,
                                             int l, int L) {
     const int sh = 2 * (L - l);  // the prefix keeps the job bits
     const uint64_t pre = keys[i] >> sh;
-    int64_t lo = i + 1, hi = n;  // answer in [lo, hi]
+    int64_t a = i, b = n, step = 1;  // keys[a] is inside; b is outside (or n)
+    for (;;) {
+        const int64_t probe = a + step;
+        if (probe >= n) break;
+        if ((keys[probe] >> sh) != pre) {
+            b = probe;
+            break;
+        }
+        a = probe;
+        step *= 2;
+    }
+    int64_t lo = a + 1, hi = b;  // the answer lies in [lo, hi]
     while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        uint64_t pm = keys[mid] >> sh;
-        if (pm == pre) lo = mid + 1; else hi = mid;
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((keys[mid] >> sh) == pre) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
