@@ -53,6 +53,8 @@ def lib():
         L.ora_build_affinities.argtypes = [_D, C.c_int64, C.c_int32, C.c_double, C.c_int32,
                                            _I32, _I64, _I32, _D, C.c_int64, _I64]
         L.ora_kl_cost.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double, _D]
+        L.ora_cosne_cost.argtypes = [_D, C.c_int64, _I64, _I32, _D, _D, C.c_double, C.c_double, _D]
+        L.ora_cosne_gradient.argtypes = [_D, C.c_int64, _D, C.c_double, C.c_double, _D, _D]
         L.ora_gradient_exact.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double, _D, _D]
         L.ora_gradient_exact_rows.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double,
                                               _I64, C.c_int64, C.c_double, _D]
@@ -187,6 +189,25 @@ def build_affinities(X, perplexity: float = 30.0, k: int = 90):
 def _csr(rp, col, val):
     return (np.ascontiguousarray(rp, dtype=np.int64), np.ascontiguousarray(col, dtype=np.int32),
             _f64(val))
+
+
+def cosne_cost(Y, rp, col, val, xnorm2, lambda1: float, lambda2: float) -> float:
+    Y = _f64(Y).reshape(-1, 2)
+    rp, col, val = _csr(rp, col, val)
+    xn = _f64(xnorm2)
+    c = np.zeros(1)
+    _check(lib().ora_cosne_cost(_p(Y, _D), Y.shape[0], _p(rp, _I64), _p(col, _I32), _p(val, _D),
+                                _p(xn, _D), float(lambda1), float(lambda2), _p(c, _D)), "cosne_cost")
+    return float(c[0])
+
+
+def cosne_gradient(Y, xnorm2, lambda1: float, lambda2: float, g_kl) -> np.ndarray:
+    Y = _f64(Y).reshape(-1, 2)
+    xn, gk = _f64(xnorm2), _f64(g_kl).reshape(-1, 2)
+    g = np.zeros_like(Y)
+    _check(lib().ora_cosne_gradient(_p(Y, _D), Y.shape[0], _p(xn, _D), float(lambda1),
+                                    float(lambda2), _p(gk, _D), _p(g, _D)), "cosne_gradient")
+    return g
 
 
 def kl_cost(Y, rp, col, val, exaggeration: float = 1.0) -> float:

@@ -349,6 +349,44 @@ int ora_kl_cost(const double *Y, int64_t n, const int64_t *row_ptr,
     return 0;
 }
 
+/* CO-SNE (Sec. 3): the cost lambda1 KL(P||Q) + (lambda2 / n) sum_i
+ * (|x_i|^2 - |y_i|^2)^2, with xnorm2[i] = |x_i|^2 of the input point.
+ * reading: the printed variation of the second part has the sign of
+ * +(4 lambda2 / n)(|x_i|^2 - |y_i|^2) y_i; the derivative of the stated cost is
+ * -(4 lambda2 / n)(|x_i|^2 - |y_i|^2) y_i, which is what is used (the finite
+ * differences of the cost decide it). */
+int ora_cosne_cost(const double *Y, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                   const double *val, const double *xnorm2, double lambda1, double lambda2,
+                   double *cost_out) {
+    if (n < 2 || !xnorm2) return -1;
+    double kl = 0.0;
+    int rc = ora_kl_cost(Y, n, row_ptr, col, val, 1.0, &kl);
+    if (rc != 0) return rc;
+    double h = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double y2 = Y[2 * i] * Y[2 * i] + Y[2 * i + 1] * Y[2 * i + 1];
+        double e = xnorm2[i] - y2;
+        h += e * e;
+    }
+    *cost_out = lambda1 * kl + lambda2 / (double)n * h;
+    return 0;
+}
+
+/* gradient of ora_cosne_cost from the KL gradient g_kl (exact or
+ * Barnes-Hut): g = lambda1 g_kl - (4 lambda2 / n)(|x_i|^2 - |y_i|^2) y_i */
+int ora_cosne_gradient(const double *Y, int64_t n, const double *xnorm2, double lambda1,
+                       double lambda2, const double *g_kl, double *g_out) {
+    if (n < 1 || !xnorm2 || !g_kl || !g_out) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        double y2 = Y[2 * i] * Y[2 * i] + Y[2 * i + 1] * Y[2 * i + 1];
+        double c = 4.0 * lambda2 / (double)n * (xnorm2[i] - y2);
+        g_out[2 * i] = lambda1 * g_kl[2 * i] - c * Y[2 * i];
+        g_out[2 * i + 1] = lambda1 * g_kl[2 * i + 1] - c * Y[2 * i + 1];
+    }
+    return 0;
+}
+
+
 /* One pair's term w^m d (d d_ij / d y_i), the common factor of both sums of
  * eq. (15).  reading: eq. (14) prints (1 + d^2)^-1 dd/dy; the derivative of
  * ln (1 + d^2)^-1 is -2 d (1 + d^2)^-1 dd/dy, so the factor d_ij is kept. */

@@ -46,6 +46,13 @@ int ora_build_affinities(const double *X, int64_t n, int32_t d, double perplexit
 int ora_kl_cost(const double *Y, int64_t n, const int64_t *row_ptr,
                 const int32_t *col, const double *val, double exaggeration,
                 double *cost_out);
+/* CO-SNE (Sec. 3): cost lambda1 KL + (lambda2/n) sum (|x_i|^2 - |y_i|^2)^2 and
+ * its gradient from a KL gradient g_kl */
+int ora_cosne_cost(const double *Y, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                   const double *val, const double *xnorm2, double lambda1, double lambda2,
+                   double *cost_out);
+int ora_cosne_gradient(const double *Y, int64_t n, const double *xnorm2, double lambda1,
+                       double lambda2, const double *g_kl, double *g_out);
 int ora_gradient_exact(const double *Y, int64_t n, const int64_t *row_ptr,
                        const int32_t *col, const double *val,
                        double exaggeration, double *grad, double *z_out);

@@ -152,3 +152,44 @@ def test_bh_error_band_and_growth():
         errs[th] = _rel(gb, ge)
     assert errs[0.3] < errs[0.5] < errs[0.8]
     assert lo / 30 < errs[0.5] < hi * 10, (errs, lo, hi)
+
+
+# ---------------------------------------------------------------- CO-SNE (Sec. 3)
+def _fd(fun, Y):
+    fd = np.zeros_like(Y)
+    for i in range(Y.shape[0]):
+        h = 1e-6 * (1 - Y[i] @ Y[i])
+        for c in range(2):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[i, c] += h
+            Ym[i, c] -= h
+            fd[i, c] = (fun(Yp) - fun(Ym)) / (2 * h)
+    return fd
+
+
+@pytest.mark.parametrize("lam1,lam2", [(1.0, 0.5), (0.3, 4.0), (1.0, 0.0)])
+def test_cosne_gradient_is_the_cost_derivative(lam1, lam2):
+    Y, rp, col, val = _problem(36, seed=3, stage="late")
+    g = synth.rng(4)
+    xn2 = g.uniform(0.0, 0.9, size=Y.shape[0])
+    gk, _ = oracle.gradient_exact(Y, rp, col, val, 1.0)
+    got = oracle.cosne_gradient(Y, xn2, lam1, lam2, gk)
+    fd = _fd(lambda Z: oracle.cosne_cost(Z, rp, col, val, xn2, lam1, lam2), Y)
+    assert np.linalg.norm(got - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_cosne_printed_sign_fails_fd():
+    # the variation as printed, +(4 lambda2 / n)(|x|^2 - |y|^2) y, is not the
+    # derivative of the stated cost
+    Y, rp, col, val = _problem(36, seed=5, stage="mid")
+    xn2 = synth.rng(6).uniform(0.0, 0.9, size=Y.shape[0])
+    gk, _ = oracle.gradient_exact(Y, rp, col, val, 1.0)
+    n, lam2 = Y.shape[0], 3.0
+    printed = gk + (4 * lam2 / n) * (xn2 - np.sum(Y * Y, 1))[:, None] * Y
+    fd = _fd(lambda Z: oracle.cosne_cost(Z, rp, col, val, xn2, 1.0, lam2), Y)
+    assert np.linalg.norm(printed - fd) / np.linalg.norm(fd) > 1e-2
+    # the norm term alone: at |y_i|^2 = |x_i|^2 it vanishes
+    Z = Y.copy()
+    xs = np.sum(Z * Z, 1)
+    zero = oracle.cosne_gradient(Z, xs, 0.0, lam2, gk)
+    assert np.abs(zero).max() < 1e-15
