@@ -193,6 +193,17 @@ hts_status hts_gradient_bh_jobs(hts_ctx ctx, hts_stream stream, const void *Y,
                                 double theta, void *grad, double *z_dev,
                                 uint64_t *stats_dev);
 
+/* CO-SNE variant (Sec. 3): turns the KL gradient in grad (from either
+ * gradient call, same Y) into the gradient of
+ *   lambda1 KL(P||Q) + (lambda2 / n) sum_i (|x_i|^2 - |y_i|^2)^2,
+ * in place: grad_i <- lambda1 grad_i - (4 lambda2 / n)(|x_i|^2 - |y_i|^2) y_i,
+ * the derivative of that cost (the paper prints the second term with the
+ * opposite sign).  xnorm2: device double[n], the squared norms of the input
+ * points as the caller defines them; lambda2 >= 0. */
+hts_status hts_cosne_terms(hts_ctx ctx, hts_stream stream, const void *Y,
+                           int64_t n, int32_t dtype, const double *xnorm2,
+                           double lambda1, double lambda2, void *grad);
+
 /* ------------------------------------------------------------------------
  * Riemannian step -- eqs. (7), (16)-(18) and the optimiser of Sec. 5.  In
  * place on Y, update and gains (n x 2 each):

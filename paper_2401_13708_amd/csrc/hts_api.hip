@@ -495,6 +495,23 @@ hts_status hts_gradient_bh_jobs(hts_ctx c, hts_stream stream, const void *Y, int
                           exaggeration_dev, t, theta, (float *)grad, z_dev, stats_dev);
 }
 
+// ---------------------------------------------------------------- CO-SNE
+hts_status hts_cosne_terms(hts_ctx c, hts_stream stream, const void *Y, int64_t n, int32_t dtype,
+                           const double *xnorm2, double lambda1, double lambda2, void *grad) {
+    if (!c) return fail(HTS_EINVAL, "hts_cosne_terms: ctx is NULL");
+    if (n < 1) return fail(HTS_EINVAL, "hts_cosne_terms: n < 1");
+    if (!dtype_ok(dtype)) return fail(HTS_EINVAL, "hts_cosne_terms: bad dtype");
+    if (!Y || !xnorm2 || !grad) return fail(HTS_EINVAL, "hts_cosne_terms: NULL pointer argument");
+    if (!std::isfinite(lambda1) || !std::isfinite(lambda2) || lambda2 < 0.0)
+        return fail(HTS_EINVAL, "hts_cosne_terms: lambda1 must be finite and lambda2 >= 0");
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == HTS_F64)
+        return launch_cosne<double>(c, st, (const double *)Y, n, xnorm2, lambda1, lambda2,
+                                    (double *)grad);
+    return launch_cosne<float>(c, st, (const float *)Y, n, xnorm2, lambda1, lambda2, (float *)grad);
+}
+
 // ---------------------------------------------------------------- step
 hts_status hts_step(hts_ctx c, hts_stream stream, void *Y, void *update, void *gains,
                     const void *grad, int64_t n, int32_t dtype, double eta, double momentum,

@@ -205,6 +205,10 @@ hts_status launch_finalize(hts_ctx ctx, hipStream_t st, const T *fattr, const FR
                            const double *zpart, int64_t nz, int64_t n, double ex, T *grad,
                            double *z_dev);
 
+template <typename T>
+hts_status launch_cosne(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, const double *xnorm2,
+                        double lambda1, double lambda2, T *grad);
+
 // eta_job / mu_job: per-job values (device, indexed through pjob) or NULL
 template <typename T>
 hts_status launch_step(hts_ctx ctx, hipStream_t st, T *Y, T *U, T *G, const T *grad, int64_t n,

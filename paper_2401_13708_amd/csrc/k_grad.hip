@@ -282,6 +282,36 @@ hts_status launch_step(hts_ctx ctx, hipStream_t st, T *Y, T *U, T *G, const T *g
     return HTS_OK;
 }
 
+// ---------------------------------------------------------------- CO-SNE
+// Sec. 3: gradient of lambda1 KL + (lambda2 / n) sum (|x_i|^2 - |y_i|^2)^2
+// from the KL gradient in grad, in place:
+//   grad_i <- lambda1 grad_i - (4 lambda2 / n)(|x_i|^2 - |y_i|^2) y_i
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cosne(const T *__restrict__ Y, int64_t n,
+                                                  const double *__restrict__ xnorm2, double l1,
+                                                  double c, T *__restrict__ grad,
+                                                  uint32_t *__restrict__ err) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double y0 = (double)Y[2 * i], y1 = (double)Y[2 * i + 1];
+    const double e = c * (xnorm2[i] - (y0 * y0 + y1 * y1));
+    const T g0 = (T)(l1 * (double)grad[2 * i] - e * y0);
+    const T g1 = (T)(l1 * (double)grad[2 * i + 1] - e * y1);
+    if (!isfinite(g0) || !isfinite(g1)) atomicOr(err, HTS_ERR_NONFINITE_GRAD);
+    grad[2 * i] = g0;
+    grad[2 * i + 1] = g1;
+}
+
+template <typename T>
+hts_status launch_cosne(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, const double *xnorm2,
+                        double lambda1, double lambda2, T *grad) {
+    TimedScope ts(ctx, st, HTS_K_FINALIZE);
+    hipLaunchKernelGGL(k_cosne<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, Y, n, xnorm2,
+                       lambda1, 4.0 * lambda2 / (double)n, grad, ctx->d_err);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
 #define HTS_INST(T)                                                                              \
     template hts_status launch_prep_points<T>(hts_ctx, hipStream_t, const T *, int64_t,           \
                                               PointRec<T> *);                                    \
@@ -293,6 +323,8 @@ hts_status launch_step(hts_ctx ctx, hipStream_t st, T *Y, T *U, T *G, const T *g
     template hts_status launch_finalize<T, T>(hts_ctx, hipStream_t, const T *, const T *,         \
                                               const double *, int64_t, int64_t, double, T *,      \
                                               double *);                                         \
+    template hts_status launch_cosne<T>(hts_ctx, hipStream_t, const T *, int64_t,                \
+                                        const double *, double, double, T *);                     \
     template hts_status launch_step<T>(hts_ctx, hipStream_t, T *, T *, T *, const T *, int64_t,   \
                                        double, double, const int32_t *, const double *,          \
                                        const double *, double, double, int);

@@ -53,6 +53,7 @@ _SIGS = {
     "hts_step_jobs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _I32, _P, _P, _D, _D, _I32]),
     "hts_jobs_schedule": (C.c_int, [_P, _P, _I32, _P, _I32, _D, _D, _D, _P, _P]),
     "hts_set_item_points": (C.c_int, [_P, _I32]),
+    "hts_cosne_terms": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _D, _D, _P]),
     "hts_tree_set_split": (C.c_int, [_P, _I32]),
     "hts_timing_enable": (C.c_int, [_P, _I32]),
     "hts_timing_read": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_I64)]),
@@ -327,3 +328,13 @@ def jobs_schedule(ctx: Context, it, ee_iters: int, exaggeration: float, momentum
     _ck(lib().hts_jobs_schedule(ctx.h, _stream(stream), it.numel(), _ptr(it), int(ee_iters),
                                 float(exaggeration), float(momentum_early), float(momentum_late),
                                 _ptr(ex_out), _ptr(mu_out)))
+
+
+def cosne_terms(ctx: Context, Y, xnorm2, lambda1: float, lambda2: float, grad, stream=None):
+    """CO-SNE gradient from the KL gradient in grad (in place)."""
+    _dev(Y, "Y")
+    _dev(grad, "grad", Y.dtype)
+    _dev(xnorm2, "xnorm2", torch.float64)
+    _ck(lib().hts_cosne_terms(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
+                              _ptr(xnorm2), float(lambda1), float(lambda2), _ptr(grad)))
+    return grad

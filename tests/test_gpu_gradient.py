@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2401_13708_amd import hts
+from paper_2401_13708_amd import hts, synth
 from gpu_inputs import STAGES, affinities, embedding, rel
 
 pytestmark = pytest.mark.gpu
@@ -158,3 +158,23 @@ def test_bh_equal_area_matches_oracle_bh(ctx, stage):
     assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
     assert rel(g, go) < 1e-10
     assert z == pytest.approx(zo, rel=1e-10)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("theta", [0.0, 0.5])
+def test_cosne_terms_match_oracle(ctx, dtype, theta):
+    # CO-SNE (Sec. 3) on top of the Barnes-Hut (theta = 0.5) or exact
+    # (theta = 0) KL gradient, against the oracle's at the same theta
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, "late", dtype)
+    xn2 = synth.rng(12).uniform(0.0, 0.95, size=1000)
+    v = val.astype(dtype)
+    g, z = _run_bh(ctx, Y, rp, col, v, 1.0, theta)
+    gd = torch.from_numpy(g).cuda()
+    hts.cosne_terms(ctx, _dev(Y), torch.from_numpy(xn2).cuda(), 0.7, 2.0, gd)
+    torch.cuda.synchronize()
+    assert ctx.check() == 0
+    Yo = Y.astype(np.float64)
+    gk, _, _ = oracle.gradient_bh(Yo, rp, col, v.astype(np.float64), oracle.Tree(Yo), theta, 1.0)
+    go = oracle.cosne_gradient(Yo, xn2, 0.7, 2.0, gk)
+    assert rel(gd.cpu().numpy(), go) < (1e-3 if dtype == np.float32 else 1e-10)
