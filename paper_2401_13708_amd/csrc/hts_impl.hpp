@@ -182,6 +182,12 @@ inline Jobs jobs_of(hts_tree t) {
 
 hts_status tree_thresholds(hts_ctx ctx, hipStream_t st, hts_tree t, int dtype, double theta);
 
+// stable LSD radix sort of (key, value) pairs by the low `bits` key bits
+size_t radix_sort_temp_bytes(int64_t n);
+hts_status radix_sort_pairs(hipStream_t st, uint64_t *keys_io, uint32_t *vals_io,
+                            uint64_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
+                            void *tmp);
+
 template <typename T>
 hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, const int64_t *rp,
                           const int32_t *col, const T *val, int64_t n, T *fattr);

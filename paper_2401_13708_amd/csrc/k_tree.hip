@@ -7,7 +7,7 @@
 //     level (radial bit: r at or above the radial split of eq. (10), or of
 //     eq. (9) when the tree is set to equal areas; angular bit:
 //     phi >= (lo + hi) / 2), most significant level first;
-//  3. stable radix sort of (key, index);
+//  3. stable radix sort of (key, index) (k_sort.hip);
 //  4. per sorted position: how many nodes start there (from the common
 //     prefixes with both neighbours), the sorted point record and the
 //     Einstein-midpoint summands, with block aggregates;
@@ -22,8 +22,6 @@
 // key bits above the cell bits, so the sort groups each job's points, no cell
 // spans two jobs, and the pre-order array is the concatenation of the jobs'
 // trees.  Every job has its own root annulus.
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include "hts_impl.hpp"
 #include "hts_math.hpp"
 
@@ -499,9 +497,8 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kBlock), 0, st, t->r, t->phi, n, t->pjob, t->root, L,
                        t->split_rule, t->keys_in, t->idx_in);
     HTS_HIP(hipGetLastError());
-    size_t bytes = t->sort_tmp_bytes;
-    HTS_HIP(rocprim::radix_sort_pairs(t->sort_tmp, bytes, t->keys_in, t->keys, t->idx_in, t->perm,
-                                      (size_t)n, 0u, (unsigned)(2 * L + t->job_bits), st));
+    HTS_OKR(radix_sort_pairs(st, t->keys_in, t->idx_in, t->keys, t->perm, n, 2 * L + t->job_bits,
+                             t->sort_tmp));
     hipLaunchKernelGGL(k_sorted<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->keys, t->perm, L,
                        (PointRec<T> *)t->spts, t->node_start, t->psum, t->ncnt_part, t->q_part);
     HTS_HIP(hipGetLastError());
@@ -521,13 +518,10 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     return HTS_OK;
 }
 
-// temporary storage of the sort, sized for the widest key (cell bits plus
-// up to 24 job bits)
+// temporary storage of the sort
 hts_status tree_sort_bytes(int64_t n_max, int L, size_t *bytes) {
-    *bytes = 0;
-    HTS_HIP(rocprim::radix_sort_pairs(nullptr, *bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                      (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n_max, 0u,
-                                      (unsigned)(2 * L + 24), (hipStream_t)0));
+    (void)L;
+    *bytes = radix_sort_temp_bytes(n_max);
     return HTS_OK;
 }
 
