@@ -91,8 +91,9 @@ class JobBatch:
             self.tree = hts.Tree(ctx, max(N, n_max or 0), max_depth)
         self.tree.set_jobs(sizes)
         self.iters_done = 0
+        self.graph = None
 
-    def iterate(self, stats=None):
+    def _launch(self, stats=None):
         s = self.sched
         hts.jobs_schedule(self.ctx, self.it, s.ee_iters, s.exaggeration, s.momentum_early,
                           s.momentum_late, self.ex, self.mu)
@@ -101,7 +102,27 @@ class JobBatch:
                              self.theta, self.grad, self.z, stats)
         hts.step_jobs(self.ctx, self.tree, self.Y, self.update, self.gains, self.grad, self.eta,
                       self.mu, s.min_gain, s.boundary_eps, s.metric_power)
+
+    def iterate(self, stats=None):
+        if self.graph is not None and stats is None:
+            self.graph.replay()
+        else:
+            self._launch(stats)
         self.iters_done += 1
+
+    def capture(self):
+        """Records one iteration of all jobs (schedule, tree, gradient, step:
+        every kernel of it, no memory clears or allocations) as a HIP graph,
+        which `iterate` then replays.  The iteration before the capture runs
+        eagerly so that the library's workspaces exist; the per-job iteration
+        counters live on the device, so every replay is the next iteration."""
+        self.iterate()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._launch()
+        self.graph = g
+        return self
 
     def run(self, iters: int):
         for _ in range(iters):
@@ -118,9 +139,11 @@ class JobBatch:
     def release_tree(self) -> hts.Tree:
         """Hands the tree to the next layout."""
         t, self.tree = self.tree, None
+        self.graph = None
         return t
 
     def close(self):
+        self.graph = None
         if self.tree is not None:
             self.tree.close()
             self.tree = None

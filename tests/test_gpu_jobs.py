@@ -211,3 +211,32 @@ def test_set_jobs_validation(ctx):
     with pytest.raises(hts.HTSError):
         hts.build_polar_tree(ctx, Y, t)      # 80 points, the layout holds 90
     t.close()
+
+
+def test_graph_replays_equal_eager_iterations(ctx):
+    # one iteration of all jobs captured as a HIP graph and replayed: every
+    # replay equals the eager iteration, with other GPU work in between
+    sizes = [700, 2, 3000, 65]
+    jobs = []
+    for j, n in enumerate(sizes):
+        Y0 = synth.disk_uniform(n, 1e-4, seed=90 + j)
+        rp, col, val = synth.random_csr(n, min(30, n - 1), seed=95 + j, dtype=np.float32)
+        jobs.append(Job(_d(rp), _d(col), _d(val), _d(Y0)))
+    start = [0, 245, 0, 10]
+    eager = JobBatch(ctx, jobs, start_iter=start)
+    want = []
+    for _ in range(12):
+        eager.iterate()
+        want.append(eager.Y.clone())
+    torch.cuda.synchronize()
+    b = JobBatch(ctx, jobs, start_iter=start).capture()     # the first iteration runs eagerly
+    assert torch.equal(b.Y, want[0])
+    scratch = torch.ones(1 << 20, device="cuda")
+    for k in range(1, 12):
+        b.iterate()
+        scratch.mul_(1.0001)                                   # unrelated work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(b.Y, want[k]), k
+    assert ctx.check() == 0
+    eager.close()
+    b.close()
