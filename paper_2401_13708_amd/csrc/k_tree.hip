@@ -12,8 +12,9 @@
 //     prefixes with both neighbours), the sorted point record and the
 //     Einstein-midpoint summands, with block aggregates;
 //  5. exclusive scans (node offsets; double-double summand sums);
-//  6. node emission in depth-first pre-order: counts, subtree ends, leaves,
-//     midpoints (eq. (11)) and cell diameters.
+//  6. node emission in depth-first pre-order: each node's first point, then
+//     per node its count, subtree end, leaf point or midpoint (eq. (11)) and
+//     cell diameter.
 // A cell becomes a node when its parent holds two or more points (the same
 // set of cells the insertion build of Sec. 2-D produces), so no insertion
 // order is involved.
@@ -367,6 +368,29 @@ __device__ __forceinline__ int64_t cell_end(const uint64_t *__restrict__ keys, i
     return lo;
 }
 
+// 6a. every node records the sorted position of its first point (a point
+// starts the nodes of depths s..D, stored consecutively from node_start[i])
+__global__ __launch_bounds__(kBlock) void k_emit_first(const uint64_t *__restrict__ keys, int64_t n,
+                                                       int L, const int32_t *__restrict__ node_start,
+                                                       int32_t *__restrict__ node_first, int64_t cap,
+                                                       uint32_t *__restrict__ err) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const NodeSpan sp = node_span(keys, i, n, L);
+    const int32_t base = node_start[i];
+    for (int l = sp.s; l <= sp.D; ++l) {
+        const int32_t k = base + (l - sp.s);
+        if (k >= cap) {  // cannot happen for a consistent scan; never write past the storage
+            atomicOr(err, HTS_ERR_TREE_OVERFLOW);
+            return;
+        }
+        node_first[k] = (int32_t)i;
+    }
+}
+
+// 6b. one thread per node: count, subtree end, leaf point or Einstein
+// midpoint, and cell diameter (threads of a wave do equal work, whatever the
+// length of their points' chains of nodes)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ keys, int64_t n, int L,
                                                  const PointRec<T> *__restrict__ spts,
@@ -376,70 +400,59 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
                                                  const double *__restrict__ sinhalf,
                                                  NodeRec<T> *__restrict__ nodes,
                                                  double *__restrict__ r_cell,
-                                                 int32_t *__restrict__ node_first,
-                                                 int64_t cap, uint32_t *__restrict__ err,
-                                                 int split) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    NodeSpan sp = node_span(keys, i, n, L);
-    if (sp.D < sp.s) return;
-    int32_t M = node_start[n];
-    int32_t base = node_start[i];
-    uint64_t key = keys[i];
+                                                 const int32_t *__restrict__ node_first,
+                                                 const int32_t *__restrict__ d_m, int split) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t M = *d_m;
+    if (k >= M) return;
+    const int64_t i = node_first[k];
+    const NodeSpan sp = node_span(keys, i, n, L);
+    const int l = sp.s + (int)(k - node_start[i]);
+    const uint64_t key = keys[i];
+    const bool leaf = (l == sp.D);
+    const int64_t end = (leaf && l < L) ? i + 1 : cell_end(keys, i, n, l, L);
+    const int32_t count = (int32_t)(end - i);
+    const int32_t next = end < n ? node_start[end] : M;
+    NodeRec<T> rec;
+    rec.count = count;
+    rec.next_depth = (uint32_t)next | ((uint32_t)l << kNextBits);
+    if constexpr (sizeof(T) == 8) rec.pad = 0.0;
+    if (leaf && count == 1) {
+        const PointRec<T> p = spts[i];
+        rec.mx = p.x;
+        rec.my = p.y;
+        rec.ib = p.ia;
+    } else {
+        // Einstein midpoint, eq. (11): Klein average then back to the disk
+        const DD3 se = psum[end], si = psum[i];
+        const double sx = dd_diff(se, si, 0), sy = dd_diff(se, si, 1), sg = dd_diff(se, si, 2);
+        const double kx = sx / sg, ky = sy / sg;
+        const double den = 1.0 + sqrt(fmax(0.0, 1.0 - (kx * kx + ky * ky)));
+        const T mx = (T)(kx / den), my = (T)(ky / den);
+        rec.mx = mx;
+        rec.my = my;
+        rec.ib = 1.0 / (1.0 - ((double)mx * (double)mx + (double)my * (double)my));
+    }
+    rec.c = leaf ? __longlong_as_double((long long)i) : 0.0;
+    nodes[k] = rec;
+    // radial bounds of the cell (same arithmetic as the keys)
     const int64_t job = (int64_t)(key >> (2 * L));
     double lo = root[2 * job], hi = root[2 * job + 1];
-    int lev = 0;  // levels replayed into (lo, hi)
-    for (int l = sp.s; l <= sp.D; ++l) {
-        int32_t k = base + (l - sp.s);
-        if (k >= cap) {  // cannot happen for a consistent scan; never write past the storage
-            atomicOr(err, HTS_ERR_TREE_OVERFLOW);
-            return;
-        }
-        bool leaf = (l == sp.D);
-        int64_t end = (leaf && l < L) ? i + 1 : cell_end(keys, i, n, l, L);
-        int32_t count = (int32_t)(end - i);
-        int32_t next = end < n ? node_start[end] : M;
-        NodeRec<T> rec;
-        rec.count = count;
-        rec.next_depth = (uint32_t)next | ((uint32_t)l << kNextBits);
-        if constexpr (sizeof(T) == 8) rec.pad = 0.0;
-        if (leaf && count == 1) {
-            PointRec<T> p = spts[i];
-            rec.mx = p.x;
-            rec.my = p.y;
-            rec.ib = p.ia;
-        } else {
-            // Einstein midpoint, eq. (11): Klein average then back to the disk
-            DD3 se = psum[end], si = psum[i];
-            double sx = dd_diff(se, si, 0), sy = dd_diff(se, si, 1), sg = dd_diff(se, si, 2);
-            double kx = sx / sg, ky = sy / sg;
-            double den = 1.0 + sqrt(fmax(0.0, 1.0 - (kx * kx + ky * ky)));
-            T mx = (T)(kx / den), my = (T)(ky / den);
-            rec.mx = mx;
-            rec.my = my;
-            rec.ib = 1.0 / (1.0 - ((double)mx * (double)mx + (double)my * (double)my));
-        }
-        rec.c = leaf ? __longlong_as_double((long long)i) : 0.0;
-        nodes[k] = rec;
-        node_first[k] = (int32_t)i;
-        // radial bounds of the cell (same arithmetic as the keys)
-        while (lev < l) {
-            int rb = (int)((key >> (2 * (L - 1 - lev) + 1)) & 1u);
-            double mr = radial_mid(lo, hi, split);
-            if (rb) lo = mr; else hi = mr;
-            ++lev;
-        }
-        // hyperbolic diameter: the larger of the outer-arc chord and the
-        // diagonal (the radial edge is never longer than the diagonal); the
-        // angular half-width is capped at pi/2 for the two top levels
-        double s = sinhalf[l];
-        double ahi = 1.0 - hi * hi, alo = 1.0 - lo * lo;
-        double t_outer = 8.0 * hi * hi * s * s / (ahi * ahi);
-        double dr = hi - lo;
-        double t_diag = 2.0 * (dr * dr + 4.0 * lo * hi * s * s) / (alo * ahi);
-        double t = fmax(t_outer, t_diag);
-        r_cell[k] = log1p(t + sqrt(t * (t + 2.0)));
+    for (int lev = 0; lev < l; ++lev) {
+        const int rb = (int)((key >> (2 * (L - 1 - lev) + 1)) & 1u);
+        const double mr = radial_mid(lo, hi, split);
+        if (rb) lo = mr; else hi = mr;
     }
+    // hyperbolic diameter: the larger of the outer-arc chord and the
+    // diagonal (the radial edge is never longer than the diagonal); the
+    // angular half-width is capped at pi/2 for the two top levels
+    const double s = sinhalf[l];
+    const double ahi = 1.0 - hi * hi, alo = 1.0 - lo * lo;
+    const double t_outer = 8.0 * hi * hi * s * s / (ahi * ahi);
+    const double dr = hi - lo;
+    const double t_diag = 2.0 * (dr * dr + 4.0 * lo * hi * s * s) / (alo * ahi);
+    const double t = fmax(t_outer, t_diag);
+    r_cell[k] = log1p(t + sqrt(t * (t + 2.0)));
 }
 
 // criterion threshold per internal node: r_cell / d < theta  <=>  t > cosh(r_cell / theta) - 1
@@ -508,10 +521,15 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, st, t->node_start, t->psum, n,
                        t->ncnt_part, t->q_part);
     HTS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_emit<T>, dim3(nb), dim3(kBlock), 0, st, t->keys, n, L,
+    hipLaunchKernelGGL(k_emit_first, dim3(nb), dim3(kBlock), 0, st, t->keys, n, L, t->node_start,
+                       t->node_first, t->cap_nodes, ctx->d_err);
+    HTS_HIP(hipGetLastError());
+    // over the node capacity for n points; the kernel reads the live count
+    int64_t nbm = cdiv(n * (int64_t)(L + 1) + 1, kBlock);
+    if (nbm > cdiv(t->cap_nodes, kBlock)) nbm = cdiv(t->cap_nodes, kBlock);
+    hipLaunchKernelGGL(k_emit<T>, dim3(nbm), dim3(kBlock), 0, st, t->keys, n, L,
                        (const PointRec<T> *)t->spts, t->node_start, t->psum, t->root, t->sinhalf,
-                       (NodeRec<T> *)t->nodes, t->r_cell, t->node_first, t->cap_nodes,
-                       ctx->d_err, t->split_rule);
+                       (NodeRec<T> *)t->nodes, t->r_cell, t->node_first, t->d_m, t->split_rule);
     HTS_HIP(hipGetLastError());
     t->n = n;
     t->dtype = sizeof(T) == 8 ? HTS_F64 : HTS_F32;
