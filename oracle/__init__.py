@@ -73,6 +73,12 @@ def lib():
         L.ora_tree_export.argtypes = [C.c_void_p, _I32, _I32, _I32, _I32, _D, _D, _D, _I64]
         L.ora_gradient_bh.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double, C.c_void_p,
                                       C.c_double, _D, _D, _I64]
+        L.ora_euclid_cost.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double, _D]
+        L.ora_gradient_euclid_exact.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double, _D,
+                                                _D]
+        L.ora_gradient_euclid_bh.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double,
+                                             C.c_void_p, C.c_double, _D, _D, _I64]
+        L.ora_tree_export_euclid.argtypes = [C.c_void_p, _D, _D]
         L.ora_step.argtypes = [_D, _D, _D, _D, C.c_int64, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_int32]
         L.ora_set_threads.argtypes = [C.c_int32]
@@ -277,6 +283,13 @@ class Tree:
                                      _p(out["bounds"], _D), _p(out["perm"], _I64)), "tree_export")
         return out
 
+    def export_euclid(self):
+        """Per node (pre-order): Euclidean centre of mass and Euclidean diameter."""
+        m = self.n_nodes
+        cent, diam = np.zeros((m, 2)), np.zeros(m)
+        _check(lib().ora_tree_export_euclid(self.h, _p(cent, _D), _p(diam, _D)), "export_euclid")
+        return cent, diam
+
     def __del__(self):
         try:
             if self.h:
@@ -296,6 +309,54 @@ def gradient_bh(Y, rp, col, val, tree: Tree, theta: float, exaggeration: float =
                                  float(exaggeration), tree.h, float(theta), _p(g, _D), _p(z, _D),
                                  _p(cnt, _I64)), "gradient_bh")
     return g, float(z[0]), dict(tests=int(cnt[0]), accepts=int(cnt[1]), pairs=int(cnt[2]))
+
+
+# ---- h-SNE (Sec. 3): Euclidean Student-t term of the disk coordinates ----
+
+def euclid_cost(Y, rp, col, val, exaggeration: float = 1.0) -> float:
+    """KL(P || Q^E) with q^E proportional to (1 + |y_i - y_j|^2)^-1."""
+    Y = _f64(Y).reshape(-1, 2)
+    rp, col, val = _csr(rp, col, val)
+    c = np.zeros(1)
+    _check(lib().ora_euclid_cost(_p(Y, _D), Y.shape[0], _p(rp, _I64), _p(col, _I32), _p(val, _D),
+                                 float(exaggeration), _p(c, _D)), "euclid_cost")
+    return float(c[0])
+
+
+def gradient_euclid_exact(Y, rp, col, val, exaggeration: float = 1.0):
+    Y = _f64(Y).reshape(-1, 2)
+    rp, col, val = _csr(rp, col, val)
+    g = np.zeros_like(Y)
+    z = np.zeros(1)
+    _check(lib().ora_gradient_euclid_exact(_p(Y, _D), Y.shape[0], _p(rp, _I64), _p(col, _I32),
+                                           _p(val, _D), float(exaggeration), _p(g, _D), _p(z, _D)),
+           "gradient_euclid_exact")
+    return g, float(z[0])
+
+
+def gradient_euclid_bh(Y, rp, col, val, tree: Tree, theta: float, exaggeration: float = 1.0):
+    Y = _f64(Y).reshape(-1, 2)
+    rp, col, val = _csr(rp, col, val)
+    g = np.zeros_like(Y)
+    z = np.zeros(1)
+    cnt = np.zeros(3, dtype=np.int64)
+    _check(lib().ora_gradient_euclid_bh(_p(Y, _D), Y.shape[0], _p(rp, _I64), _p(col, _I32),
+                                        _p(val, _D), float(exaggeration), tree.h, float(theta),
+                                        _p(g, _D), _p(z, _D), _p(cnt, _I64)), "gradient_euclid_bh")
+    return g, float(z[0]), dict(tests=int(cnt[0]), accepts=int(cnt[1]), pairs=int(cnt[2]))
+
+
+def hsne_cost(Y, rp, col, val, lam: float, exaggeration: float = 1.0) -> float:
+    """h-SNE cost as read: KL(P || Q^E) + lam KL(P || Q^H)."""
+    return euclid_cost(Y, rp, col, val, exaggeration) + lam * kl_cost(Y, rp, col, val, exaggeration)
+
+
+def hsne_gradient_bh(Y, rp, col, val, tree: Tree, theta: float, lam: float,
+                     exaggeration: float = 1.0):
+    """Euclidean plus lam times hyperbolic gradient; returns (g, Z^E, Z^H)."""
+    ge, ze, _ = gradient_euclid_bh(Y, rp, col, val, tree, theta, exaggeration)
+    gh, zh, _ = gradient_bh(Y, rp, col, val, tree, theta, exaggeration)
+    return ge + lam * gh, ze, zh
 
 
 def step(Y, update, gains, grad, eta: float, momentum: float, min_gain: float = 0.01,

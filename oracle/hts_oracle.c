@@ -507,6 +507,8 @@ struct ora_tree {
     int64_t *perm;     /* points in leaf order */
     double *mid;       /* Einstein midpoints, pre-order */
     double *rcell;     /* cell diameters, pre-order */
+    double *ecent;     /* Euclidean centres of mass, pre-order (h-SNE term) */
+    double *ediam;     /* Euclidean cell diameters, pre-order (h-SNE term) */
 };
 
 /* reading: the angular position phi in [0, 2 pi) and the radius are taken
@@ -672,6 +674,30 @@ static double cell_diameter(const onode *o) {
     return best;
 }
 
+/* Euclidean diameter of a cell: the largest Euclidean distance between two
+ * of its corners, with the same reading for angular widths of pi or more as
+ * the hyperbolic diameter above (the far corner pi away from the first). */
+static double cell_diameter_euclid(const onode *o) {
+    double dphi = o->p_hi - o->p_lo;
+    if (dphi >= M_PI) dphi = M_PI;
+    double rr[2] = {o->r_lo, o->r_hi};
+    double pp[2] = {o->p_lo, o->p_lo + dphi};
+    double cx[4], cy[4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            cx[2 * a + b] = rr[a] * cos(pp[b]);
+            cy[2 * a + b] = rr[a] * sin(pp[b]);
+        }
+    double best = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b) {
+            double dx = cx[a] - cx[b], dy = cy[a] - cy[b];
+            double dd = sqrt(dx * dx + dy * dy);
+            if (dd > best) best = dd;
+        }
+    return best;
+}
+
 static int64_t g_pre_pos;
 static int64_t g_perm_pos;
 
@@ -699,7 +725,10 @@ static int finish_tree(ora_tree *t) {
     t->perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)t->n);
     t->mid = (double *)malloc(sizeof(double) * (size_t)(2 * m));
     t->rcell = (double *)malloc(sizeof(double) * (size_t)m);
-    if (!t->pre || !t->pre_first || !t->pre_next || !t->perm || !t->mid || !t->rcell)
+    t->ecent = (double *)malloc(sizeof(double) * (size_t)(2 * m));
+    t->ediam = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!t->pre || !t->pre_first || !t->pre_next || !t->perm || !t->mid || !t->rcell ||
+        !t->ecent || !t->ediam)
         return -2;
     g_pre_pos = 0;
     g_perm_pos = 0;
@@ -716,6 +745,15 @@ static int finish_tree(ora_tree *t) {
         }
         ora_einstein_midpoint(buf, o->count, &t->mid[2 * k]);
         t->rcell[k] = cell_diameter(o);
+        /* centre of mass of the cell's points in the disk coordinates */
+        double sx = 0.0, sy = 0.0;
+        for (int32_t a = 0; a < o->count; ++a) {
+            sx += buf[2 * a];
+            sy += buf[2 * a + 1];
+        }
+        t->ecent[2 * k] = sx / (double)o->count;
+        t->ecent[2 * k + 1] = sy / (double)o->count;
+        t->ediam[k] = cell_diameter_euclid(o);
     }
     free(buf);
     return 0;
@@ -804,6 +842,7 @@ void ora_tree_free(ora_tree *t) {
     free(t->px); free(t->py); free(t->r); free(t->phi);
     free(t->pre); free(t->pre_first); free(t->pre_next);
     free(t->perm); free(t->mid); free(t->rcell);
+    free(t->ecent); free(t->ediam);
     free(t);
 }
 
@@ -933,6 +972,193 @@ int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
         }
     }
     free(pos); free(fr); free(zi); free(cnt);
+    return 0;
+}
+
+/* ======================================================================
+ * h-SNE (Sec. 3): a Euclidean Student-t term on the disk coordinates
+ * ======================================================================
+ * reading: the printed h-SNE variation is the sum of a Euclidean t-SNE
+ * gradient of the disk coordinates (the form of eq. (4)) and lambda times the
+ * hyperbolic one of eq. (14); the printed minus sign in front of the second
+ * part and its missing factor d are taken as misprints (with them it would
+ * ascend the hyperbolic KL divergence).  The cost whose gradient this sum is
+ * reads KL(P || Q^E) + lambda KL(P || Q^H), with
+ * q^E_ij = (1 + |y_i - y_j|^2)^-1 / sum_{k != l} (1 + |y_k - y_l|^2)^-1.
+ * The Euclidean part is accelerated over the same polar quadtree: an internal
+ * cell is replaced by N_cell copies of its centre of mass when
+ * ediam / |y_i - c| < theta (ediam: the Euclidean cell diameter). */
+
+static double euclid_w(double ix, double iy, double jx, double jy, double *dx, double *dy) {
+    *dx = ix - jx;
+    *dy = iy - jy;
+    return 1.0 / (1.0 + (*dx) * (*dx) + (*dy) * (*dy));
+}
+
+/* Euclidean attractive sum for row i: sum_j p_ij w_ij (y_i - y_j) */
+static void euclid_attract_row(const double *Y, const int64_t *row_ptr, const int32_t *col,
+                               const double *val, int64_t i, double *fa) {
+    fa[0] = fa[1] = 0.0;
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        int64_t j = col[e];
+        if (j == i) continue;
+        double dx, dy;
+        double w = euclid_w(Y[2 * i], Y[2 * i + 1], Y[2 * j], Y[2 * j + 1], &dx, &dy);
+        fa[0] += val[e] * w * dx;
+        fa[1] += val[e] * w * dy;
+    }
+}
+
+/* KL(P || Q^E); with exaggeration a, sum a p ln(a p) - sum a p ln w + ln Z as
+ * for the hyperbolic cost */
+int ora_euclid_cost(const double *Y, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *val, double exaggeration, double *cost_out) {
+    if (n < 2) return -1;
+    double z = 0.0, dx, dy;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i) z += euclid_w(Y[2 * i], Y[2 * i + 1], Y[2 * j], Y[2 * j + 1], &dx, &dy);
+    double c = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int64_t j = col[e];
+            double p = exaggeration * val[e];
+            if (p <= 0.0) continue;
+            double w = euclid_w(Y[2 * i], Y[2 * i + 1], Y[2 * j], Y[2 * j + 1], &dx, &dy);
+            c += p * (log(p) - log(w));
+        }
+    *cost_out = c + log(z);
+    return 0;
+}
+
+/* exact Euclidean gradient: g_i = 4 sum_{j != i} (a p_ij - w_ij / Z) w_ij (y_i - y_j) */
+int ora_gradient_euclid_exact(const double *Y, int64_t n, const int64_t *row_ptr,
+                              const int32_t *col, const double *val, double exaggeration,
+                              double *grad, double *z_out) {
+    if (n < 2) return -1;
+    double *zi = (double *)malloc(sizeof(double) * (size_t)n);
+    double *fr = (double *)malloc(sizeof(double) * (size_t)(2 * n));
+    if (!zi || !fr) { free(zi); free(fr); return -2; }
+#pragma omp parallel for num_threads(NTH()) schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double rx = 0.0, ry = 0.0, sz = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx, dy;
+            double w = euclid_w(Y[2 * i], Y[2 * i + 1], Y[2 * j], Y[2 * j + 1], &dx, &dy);
+            rx += w * w * dx;
+            ry += w * w * dy;
+            sz += w;
+        }
+        fr[2 * i] = rx;
+        fr[2 * i + 1] = ry;
+        zi[i] = sz;
+    }
+    double z = 0.0;
+    for (int64_t i = 0; i < n; ++i) z += zi[i];
+    for (int64_t i = 0; i < n; ++i) {
+        double fa[2];
+        euclid_attract_row(Y, row_ptr, col, val, i, fa);
+        grad[2 * i] = 4.0 * (exaggeration * fa[0] - fr[2 * i] / z);
+        grad[2 * i + 1] = 4.0 * (exaggeration * fa[1] - fr[2 * i + 1] / z);
+    }
+    if (z_out) *z_out = z;
+    free(zi);
+    free(fr);
+    return 0;
+}
+
+/* the same depth-first traversal as bh_visit, with Euclidean distances,
+ * centres of mass and diameters */
+static void bh_visit_euclid(bh_state *s, int32_t nid) {
+    const onode *o = &s->t->nodes[nid];
+    if (o->is_leaf) {
+        for (int32_t a = 0; a < o->npts; ++a) {
+            int64_t j = o->pts[a];
+            if (j == s->i) continue;
+            double dx, dy;
+            double w = euclid_w(s->yx, s->yy, s->t->px[j], s->t->py[j], &dx, &dy);
+            s->fx += w * w * dx;
+            s->fy += w * w * dy;
+            s->z += w;
+            s->pairs++;
+        }
+        return;
+    }
+    int64_t k = s->pos_of_node[nid];
+    const double *c = &s->t->ecent[2 * k];
+    double dx, dy;
+    double w = euclid_w(s->yx, s->yy, c[0], c[1], &dx, &dy);
+    double d = sqrt(dx * dx + dy * dy);
+    s->tests++;
+    if (s->t->ediam[k] / d < s->theta) {
+        double nc = (double)o->count;
+        s->fx += nc * w * w * dx;
+        s->fy += nc * w * w * dy;
+        s->z += nc * w;
+        s->accepts++;
+        return;
+    }
+    for (int ch = 0; ch < 4; ++ch)
+        if (o->child[ch] >= 0) bh_visit_euclid(s, o->child[ch]);
+}
+
+int ora_gradient_euclid_bh(const double *Y, int64_t n, const int64_t *row_ptr,
+                           const int32_t *col, const double *val, double exaggeration,
+                           const ora_tree *t, double theta, double *grad, double *z_out,
+                           int64_t *counters) {
+    if (n < 2 || !t || t->n != n || !(theta >= 0.0) || isinf(theta)) return -1;
+    int64_t m = t->nn;
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    double *fr = (double *)malloc(sizeof(double) * (size_t)(2 * n));
+    double *zi = (double *)malloc(sizeof(double) * (size_t)n);
+    int64_t *cnt = (int64_t *)calloc((size_t)(3 * n), sizeof(int64_t));
+    if (!pos || !fr || !zi || !cnt) { free(pos); free(fr); free(zi); free(cnt); return -2; }
+    for (int64_t k = 0; k < m; ++k) pos[t->pre[k]] = k;
+#pragma omp parallel for num_threads(NTH()) schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        bh_state s;
+        memset(&s, 0, sizeof(s));
+        s.t = t;
+        s.pos_of_node = pos;
+        s.theta = theta;
+        s.i = i;
+        s.yx = Y[2 * i];
+        s.yy = Y[2 * i + 1];
+        bh_visit_euclid(&s, 0);
+        fr[2 * i] = s.fx;
+        fr[2 * i + 1] = s.fy;
+        zi[i] = s.z;
+        cnt[3 * i] = s.tests;
+        cnt[3 * i + 1] = s.accepts;
+        cnt[3 * i + 2] = s.pairs;
+    }
+    double z = 0.0;
+    for (int64_t i = 0; i < n; ++i) z += zi[i];
+    for (int64_t i = 0; i < n; ++i) {
+        double fa[2];
+        euclid_attract_row(Y, row_ptr, col, val, i, fa);
+        grad[2 * i] = 4.0 * (exaggeration * fa[0] - fr[2 * i] / z);
+        grad[2 * i + 1] = 4.0 * (exaggeration * fa[1] - fr[2 * i + 1] / z);
+    }
+    if (z_out) *z_out = z;
+    if (counters) {
+        counters[0] = counters[1] = counters[2] = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            counters[0] += cnt[3 * i];
+            counters[1] += cnt[3 * i + 1];
+            counters[2] += cnt[3 * i + 2];
+        }
+    }
+    free(pos); free(fr); free(zi); free(cnt);
+    return 0;
+}
+
+int ora_tree_export_euclid(const ora_tree *t, double *cent, double *diam) {
+    for (int64_t k = 0; k < t->nn; ++k) {
+        if (cent) { cent[2 * k] = t->ecent[2 * k]; cent[2 * k + 1] = t->ecent[2 * k + 1]; }
+        if (diam) diam[k] = t->ediam[k];
+    }
     return 0;
 }
 

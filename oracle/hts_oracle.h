@@ -90,6 +90,23 @@ int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
                     const ora_tree *t, double theta, double *grad,
                     double *z_out, int64_t *counters /* tests, accepts, leaf pairs; or NULL */);
 
+/* ---- h-SNE (Sec. 3): the Euclidean Student-t term of the disk coordinates ----
+ * cost KL(P || Q^E) with q^E_ij proportional to (1 + |y_i - y_j|^2)^-1; its
+ * exact gradient; and the same accelerated over the polar quadtree with
+ * Euclidean centres of mass and the criterion ediam / |y_i - c| < theta.
+ * The h-SNE gradient is the Euclidean one plus lambda times the hyperbolic. */
+int ora_euclid_cost(const double *Y, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *val, double exaggeration, double *cost_out);
+int ora_gradient_euclid_exact(const double *Y, int64_t n, const int64_t *row_ptr,
+                              const int32_t *col, const double *val, double exaggeration,
+                              double *grad, double *z_out);
+int ora_gradient_euclid_bh(const double *Y, int64_t n, const int64_t *row_ptr,
+                           const int32_t *col, const double *val, double exaggeration,
+                           const ora_tree *t, double theta, double *grad, double *z_out,
+                           int64_t *counters);
+/* per node (pre-order): centre of mass (n_nodes x 2) and Euclidean diameter */
+int ora_tree_export_euclid(const ora_tree *t, double *cent, double *diam);
+
 /* ---- Riemannian step (eqs. (7), (16)-(18), Sec. 5 optimiser) ---- */
 int ora_step(double *Y, double *update, double *gains, const double *grad,
              int64_t n, double eta, double momentum, double min_gain,
