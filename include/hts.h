@@ -193,6 +193,29 @@ hts_status hts_gradient_bh_jobs(hts_ctx ctx, hts_stream stream, const void *Y,
                                 double theta, void *grad, double *z_dev,
                                 uint64_t *stats_dev);
 
+/* h-SNE variant (Sec. 3).  The printed h-SNE variation is read as the sum
+ * of a Euclidean t-SNE gradient of the disk coordinates and lambda times the
+ * hyperbolic gradient above (the printed minus sign of the second part and
+ * its missing factor d taken as misprints): the gradient of
+ *   KL(P||Q^E) + lambda KL(P||Q^H),  q^E_ij = v_ij / Z^E,  v_ij = (1 + |y_i - y_j|^2)^-1,
+ *   g_i = 4 ( a sum_j p_ij v_ij (y_i - y_j) - (1/Z^E) sum_{j!=i} v_ij^2 (y_i - y_j) )
+ *         + lambda g^H_i  (g^H as from hts_gradient_bh).
+ * Both parts are accelerated over the same polar quadtree: the Euclidean
+ * part replaces a cell by N_cell copies of its centre of mass c when
+ * ediam / |y_i - c| < theta, ediam being the largest Euclidean distance
+ * between two corners of the cell (angular widths of pi or more read as pi).
+ * tree: built from the same Y, one job.  lambda: finite, >= 0.
+ * z_dev: device double[2], receives Z^E then Z^H.  stats_dev: NULL or device
+ * uint64[20]: [0..9] the counters of hts_gradient_bh for the Euclidean
+ * traversal, [10..19] for the hyperbolic one (added to).  The first call
+ * allocates the tree's Euclidean node records (cap entries). */
+hts_status hts_gradient_hsne(hts_ctx ctx, hts_stream stream, const void *Y,
+                             int64_t n, int32_t dtype, const int64_t *row_ptr,
+                             const int32_t *col_idx, const void *p_val,
+                             double exaggeration, double lambda, hts_tree tree,
+                             double theta, void *grad, double *z_dev,
+                             uint64_t *stats_dev);
+
 /* CO-SNE variant (Sec. 3): turns the KL gradient in grad (from either
  * gradient call, same Y) into the gradient of
  *   lambda1 KL(P||Q) + (lambda2 / n) sum_i (|x_i|^2 - |y_i|^2)^2,

@@ -244,7 +244,7 @@ hts_status hts_tree_destroy(hts_tree t) {
     void *ptrs[] = {t->job_off, t->job_qb, t->qb_job, t->pjob, t->root, t->r, t->phi, t->mm,
                     t->keys_in, t->keys, t->idx_in, t->perm, t->sort_tmp, t->ncnt_part,
                     t->q_part, t->node_start, t->psum, t->d_m, t->spts, t->nodes, t->r_cell,
-                    t->node_first, t->sinhalf};
+                    t->node_first, t->sinhalf, t->enodes, t->epsum, t->epart};
     for (void *p : ptrs)
         if (p) hipFree(p);
     delete t;
@@ -443,8 +443,8 @@ static hts_status bh_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, cons
     PointRec<T> *pts = (PointRec<T> *)c->pts.p;
     HTS_OKR(tree_thresholds(c, st, t, sizeof(T) == 8 ? HTS_F64 : HTS_F32, theta));
     HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
-    return launch_bh_repulsion<T>(c, st, t, n, pts, rp, col, val, (T *)c->fattr.p, ex, ex_job,
-                                  grad, z_dev, stats);
+    return launch_bh_repulsion<T, 0>(c, st, t, n, pts, rp, col, val, (T *)c->fattr.p, ex, ex_job,
+                                     false, 1.0, grad, z_dev, stats);
 }
 
 static hts_status bh_tree_args(const char *fn, hts_ctx c, hts_tree t, int64_t n, int32_t dtype,
@@ -493,6 +493,71 @@ hts_status hts_gradient_bh_jobs(hts_ctx c, hts_stream stream, const void *Y, int
                                1.0, exaggeration_dev, t, theta, (double *)grad, z_dev, stats_dev);
     return bh_impl<float>(c, st, (const float *)Y, n, row_ptr, col_idx, (const float *)p_val, 1.0,
                           exaggeration_dev, t, theta, (float *)grad, z_dev, stats_dev);
+}
+
+// ---------------------------------------------------------------- h-SNE
+}  // extern "C"
+
+static hts_status tree_euclid_alloc(hts_tree t) {
+    if (t->enodes) return HTS_OK;
+    struct A { void **p; size_t bytes; } allocs[] = {
+        {(void **)&t->enodes, (size_t)t->cap_nodes * sizeof(NodeRec<double>)},
+        {(void **)&t->epsum, ((size_t)t->n_max + 1) * sizeof(DD2)},
+        {(void **)&t->epart, (size_t)t->nb * sizeof(DD2)},
+    };
+    for (auto &a : allocs) {
+        hipError_t e = hipMalloc(a.p, a.bytes);
+        if (e != hipSuccess) {
+            for (auto &b : allocs)
+                if (*b.p) {
+                    hipFree(*b.p);
+                    *b.p = nullptr;
+                }
+            return hip_fail(e, "hipMalloc(euclidean nodes)");
+        }
+    }
+    return HTS_OK;
+}
+
+template <typename T>
+static hts_status hsne_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, const int64_t *rp,
+                            const int32_t *col, const T *val, double ex, double lambda,
+                            hts_tree t, double theta, T *grad, double *z_dev, uint64_t *stats) {
+    HTS_OKR(tree_euclid_alloc(t));
+    HTS_OKR(ensure(c->pts, (size_t)n * sizeof(PointRec<T>)));
+    HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
+    PointRec<T> *pts = (PointRec<T> *)c->pts.p;
+    T *fattr = (T *)c->fattr.p;
+    HTS_OKR(tree_thresholds(c, st, t, sizeof(T) == 8 ? HTS_F64 : HTS_F32, theta));
+    HTS_OKR(tree_euclid<T>(c, st, t, theta));
+    HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
+    // Euclidean part into grad, then grad + lambda (hyperbolic part)
+    HTS_OKR((launch_bh_repulsion<T, 1>(c, st, t, n, pts, rp, col, val, fattr, ex, nullptr, false,
+                                       1.0, grad, z_dev, stats)));
+    return launch_bh_repulsion<T, 0>(c, st, t, n, pts, rp, col, val, fattr, ex, nullptr, true,
+                                     lambda, grad, z_dev + 1, stats ? stats + 10 : nullptr);
+}
+
+extern "C" {
+hts_status hts_gradient_hsne(hts_ctx c, hts_stream stream, const void *Y, int64_t n, int32_t dtype,
+                             const int64_t *row_ptr, const int32_t *col_idx, const void *p_val,
+                             double exaggeration, double lambda, hts_tree t, double theta,
+                             void *grad, double *z_dev, uint64_t *stats_dev) {
+    HTS_OKR(grad_args("hts_gradient_hsne", c, Y, n, dtype, row_ptr, col_idx, p_val, exaggeration,
+                      grad, z_dev));
+    HTS_OKR(bh_tree_args("hts_gradient_hsne", c, t, n, dtype, theta));
+    if (t->J != 1)
+        return fail(HTS_EINVAL, "hts_gradient_hsne: the tree holds %d jobs; one is supported", t->J);
+    if (!(lambda >= 0.0) || !std::isfinite(lambda))
+        return fail(HTS_EINVAL, "hts_gradient_hsne: lambda %g must be finite and >= 0", lambda);
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == HTS_F64)
+        return hsne_impl<double>(c, st, (const double *)Y, n, row_ptr, col_idx,
+                                 (const double *)p_val, exaggeration, lambda, t, theta,
+                                 (double *)grad, z_dev, stats_dev);
+    return hsne_impl<float>(c, st, (const float *)Y, n, row_ptr, col_idx, (const float *)p_val,
+                            exaggeration, lambda, t, theta, (float *)grad, z_dev, stats_dev);
 }
 
 // ---------------------------------------------------------------- CO-SNE

@@ -68,6 +68,8 @@ struct Jobs {
 
 // double-double triple used for the prefix sums of the midpoint summands
 struct DD3 { double hi[3]; double lo[3]; };
+// double-double pair for the prefix sums of the coordinates (Euclidean centres)
+struct DD2 { double hi[2]; double lo[2]; };
 
 // ---------------------------------------------------------------- handles
 struct Timing {
@@ -132,6 +134,10 @@ struct hts_tree_s {
     double *sinhalf = nullptr;     // [32] sin(pi / 2^l), 1 for l <= 1
     int32_t job_bits = 0;          // key bits above the 2 max_depth cell bits
     int32_t split_rule = 0;        // 0: equal radial lengths (eq. (10)); 1: equal areas (eq. (9))
+    // Euclidean summaries for the h-SNE term, allocated on first use
+    void *enodes = nullptr;        // NodeRec<T>[cap_nodes]
+    hts::DD2 *epsum = nullptr;     // [n_max + 1] prefix sums of the sorted coordinates
+    hts::DD2 *epart = nullptr;     // [nb] block aggregates
 };
 
 namespace hts {
@@ -182,6 +188,11 @@ inline Jobs jobs_of(hts_tree t) {
 
 hts_status tree_thresholds(hts_ctx ctx, hipStream_t st, hts_tree t, int dtype, double theta);
 
+// Euclidean node records (centres of mass, thresholds for theta) of the last
+// build, for the h-SNE term
+template <typename T>
+hts_status tree_euclid(hts_ctx ctx, hipStream_t st, hts_tree t, double theta);
+
 // stable LSD radix sort of (key, value) pairs by the low `bits` key bits
 size_t radix_sort_temp_bytes(int64_t n);
 hts_status radix_sort_pairs(hipStream_t st, uint64_t *keys_io, uint32_t *vals_io,
@@ -194,13 +205,16 @@ hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, c
 
 // Barnes-Hut repulsion over the tree and the combine g = 4 (a F_attr - F_rep / Z)
 // ex_job: per-job exaggeration (device, [J]) or NULL for ex; z_dev receives
-// Z of every job ([J])
+// Z of every job ([J]); with accumulate, grad + scale g is stored.
+// MET 0: hyperbolic terms over the tree's nodes; MET 1: the Euclidean
+// Student-t terms over the Euclidean records of tree_euclid.
 // (the first launch also computes the attractive term into fattr)
-template <typename T>
+template <typename T, int MET>
 hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n,
                                const PointRec<T> *pts, const int64_t *rp, const int32_t *col,
-                               const T *val, T *fattr, double ex, const double *ex_job, T *grad,
-                               double *z_dev, uint64_t *stats);
+                               const T *val, T *fattr, double ex, const double *ex_job,
+                               bool accumulate, double scale, T *grad, double *z_dev,
+                               uint64_t *stats);
 
 template <typename T>
 hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,

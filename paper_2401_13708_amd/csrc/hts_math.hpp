@@ -90,6 +90,82 @@ __device__ __forceinline__ PairTerm<float> pair_term<float>(float qx, float qy, 
     return r;
 }
 
+// ---------------------------------------------------------------- metrics
+// The traversal and the attractive rows are written once over a metric:
+//  Geo<0>: the Poincare disk (eqs. (8), (13)), terms w^m d dd/dy as above;
+//  Geo<1>: the Euclidean Student-t kernel of the disk coordinates (the first
+//          part of the h-SNE gradient, Sec. 3): w = (1 + |y - o|^2)^-1, terms
+//          w^m (y - o); the criterion argument is |y - o|^2 itself.
+// arg() returns the quantity compared with a node's threshold; attract() and
+// repel() add p w (...) and N w^2 (...) to the force and N w to Z.
+template <int MET> struct Geo;
+
+template <> struct Geo<0> {
+    template <typename T>
+    static __device__ __forceinline__ double arg(const PointRec<T> &me, T ox, T oy, double oib,
+                                                 double &dd) {
+        return dist_arg<T>(me.x, me.y, me.ia, ox, oy, oib, dd);
+    }
+    template <typename T>
+    static __device__ __forceinline__ void repel(const PointRec<T> &me, T ox, T oy, double oib,
+                                                 double t, double dd, T weight, T &fx, T &fy,
+                                                 double &z) {
+        const PairTerm<T> r = pair_term<T>(me.x, me.y, me.ia, ox, oy, oib, t, dd);
+        const T coef = weight * r.w * r.w * r.base;
+        fx += coef * r.vx;
+        fy += coef * r.vy;
+        z += (double)(weight * r.w);
+    }
+    template <typename T>
+    static __device__ __forceinline__ T attract(const PointRec<T> &q, const PointRec<T> &o, T p,
+                                                T &vx, T &vy) {
+        double dd;
+        const double t = dist_arg<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, dd);
+        const PairTerm<T> r = pair_term<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, t, dd);
+        vx = r.vx;
+        vy = r.vy;
+        return p * r.w * r.base;
+    }
+};
+
+template <typename T> __device__ __forceinline__ T recip(T x) { return (T)1 / x; }
+template <> __device__ __forceinline__ float recip<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);
+}
+
+template <> struct Geo<1> {
+    template <typename T>
+    static __device__ __forceinline__ double arg(const PointRec<T> &me, T ox, T oy, double oib,
+                                                 double &dd) {
+        (void)oib;
+        const double dx = (double)me.x - (double)ox;
+        const double dy = (double)me.y - (double)oy;
+        dd = dx * dx + dy * dy;
+        return dd;
+    }
+    template <typename T>
+    static __device__ __forceinline__ void repel(const PointRec<T> &me, T ox, T oy, double oib,
+                                                 double t, double dd, T weight, T &fx, T &fy,
+                                                 double &z) {
+        (void)oib;
+        (void)t;
+        const T w = recip<T>((T)1 + (T)dd);
+        const T coef = weight * w * w;
+        fx += coef * (me.x - ox);
+        fy += coef * (me.y - oy);
+        z += (double)(weight * w);
+    }
+    template <typename T>
+    static __device__ __forceinline__ T attract(const PointRec<T> &q, const PointRec<T> &o, T p,
+                                                T &vx, T &vy) {
+        const double dx = (double)q.x - (double)o.x;
+        const double dy = (double)q.y - (double)o.y;
+        vx = q.x - o.x;
+        vy = q.y - o.y;
+        return p * recip<T>((T)1 + (T)(dx * dx + dy * dy));
+    }
+};
+
 // ---------------------------------------------------------------- wave ops
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -142,7 +218,7 @@ __device__ __forceinline__ DD3 dd_zero() {
 // F_attr,i = sum_{j in row i} p_ij w_ij d_ij dd_ij/dy_i.  G lanes share a CSR
 // row; column/value reads are contiguous per row, the point records of the
 // columns are gathered (they stay in L2).
-template <typename T, int G>
+template <typename T, int G, int MET = 0>
 __device__ __forceinline__ void attract_rows(int64_t block, const PointRec<T> *__restrict__ pts,
                                              const int64_t *__restrict__ rp,
                                              const int32_t *__restrict__ col,
@@ -163,12 +239,11 @@ __device__ __forceinline__ void attract_rows(int64_t block, const PointRec<T> *_
                 continue;
             }
             const PointRec<T> o = pts[j];
-            double dd;
-            const double t = dist_arg<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, dd);
-            const PairTerm<T> r = pair_term<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, t, dd);
-            const T coef = (j == row) ? (T)0 : p * r.w * r.base;
-            fx += coef * r.vx;
-            fy += coef * r.vy;
+            T vx, vy;
+            const T a = Geo<MET>::attract(q, o, p, vx, vy);
+            const T coef = (j == row) ? (T)0 : a;
+            fx += coef * vx;
+            fy += coef * vy;
         }
     }
     fx = group_sum<G>(fx);

@@ -56,23 +56,13 @@ struct Counters {
     unsigned long long test = 0, acc = 0, pair = 0, step = 0, work = 0;
 };
 
-template <typename T>
-__device__ __forceinline__ void add_term(const PointRec<T> &me, T ox, T oy, double oib, double t,
-                                         double dd, T weight, T &fx, T &fy, double &z) {
-    PairTerm<T> r = pair_term<T>(me.x, me.y, me.ia, ox, oy, oib, t, dd);
-    T coef = weight * r.w * r.w * r.base;
-    fx += coef * r.vx;
-    fy += coef * r.vy;
-    z += (double)(weight * r.w);
-}
-
 // Depth-first walk of the pre-order range [k, kend), which starts at a node
 // of depth d0 and holds its subtree, for the lanes in mask0.  With EMIT, an
 // internal node of at most S points that some lanes reject is appended to the
 // block's item list (while there is room) instead of being descended.
 // Node records are read with scalar loads (the node index is uniform);
 // both possible successors are fetched while a node is evaluated.
-template <typename T, bool STATS, bool EMIT>
+template <typename T, int MET, bool STATS, bool EMIT>
 __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M,
                                      const PointRec<T> *__restrict__ spts, const PointRec<T> &me,
                                      int64_t q, int lane, int k, int kend, int d0, uint64_t mask0,
@@ -100,8 +90,8 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 const bool use = in && first != q;
                 if (use) {
                     double dd;
-                    double t = dist_arg<T>(me.x, me.y, me.ia, cur.mx, cur.my, cur.ib, dd);
-                    add_term<T>(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, z);
+                    double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
+                    Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, z);
                 }
                 if (STATS) {
                     const uint64_t um = __ballot(use);
@@ -114,8 +104,8 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                     const bool use = in && (first + a) != q;
                     if (use) {
                         double dd;
-                        double t = dist_arg<T>(me.x, me.y, me.ia, o.x, o.y, o.ia, dd);
-                        add_term<T>(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, z);
+                        double t = Geo<MET>::arg(me, o.x, o.y, o.ia, dd);
+                        Geo<MET>::repel(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, z);
                     }
                     if (STATS) c.pair += __popcll(__ballot(use));
                 }
@@ -126,9 +116,9 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             bool acc = false;
             if (in) {
                 double dd;
-                double t = dist_arg<T>(me.x, me.y, me.ia, cur.mx, cur.my, cur.ib, dd);
+                double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
                 acc = t > cur.c;
-                if (acc) add_term<T>(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, z);
+                if (acc) Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, z);
             }
             const uint64_t rej = __ballot(in && !acc);
             if (STATS) {
@@ -170,7 +160,7 @@ __device__ __forceinline__ void put_stats(uint32_t *__restrict__ sp, const Count
 // These few waves are latency-bound and leave most of the chip idle, so the
 // same launch also carries the attractive term (first sum of eq. (15)), which
 // streams P: workgroups from top_blocks on compute its rows.
-template <typename T, bool STATS>
+template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_top(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
     const int32_t *__restrict__ node_start, Jobs jb, const PointRec<T> *__restrict__ spts,
@@ -182,8 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     uint32_t *__restrict__ err) {
     __shared__ LdsItem s_items[kBlock / kWave][kItemCap];
     if ((int64_t)blockIdx.x >= top_blocks) {
-        attract_rows<T, kAttractLanes>((int64_t)blockIdx.x - top_blocks, pts, rp, col, val, n,
-                                       fattr, err);
+        attract_rows<T, kAttractLanes, MET>((int64_t)blockIdx.x - top_blocks, pts, rp, col, val,
+                                            n, fattr, err);
         return;
     }
     const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
@@ -207,8 +197,8 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     double z = 0.0;
     Counters c;
     int nitems = 0;
-    walk<T, STATS, true>(nodes, M, spts, me, q, lane, k0, k1, 0, __ballot(valid), S, items,
-                          nitems, fx, fy, z, c);
+    walk<T, MET, STATS, true>(nodes, M, spts, me, q, lane, k0, k1, 0, __ballot(valid), S, items,
+                               nitems, fx, fy, z, c);
     // reserve a contiguous run of the item list (one atomic per block; the
     // runs of different blocks may come in any order)
     int base = 0;
@@ -255,7 +245,7 @@ __device__ __forceinline__ ItemRec load_item(const ItemRec *__restrict__ dense, 
 }
 
 // Phase B: wave w walks items w, w + G, ... of the item list.
-template <typename T, bool STATS>
+template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_items(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
     const PointRec<T> *__restrict__ spts, const unsigned *__restrict__ dense_count,
@@ -274,9 +264,9 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
         T fx = 0, fy = 0;
         double z = 0.0;
         Counters c;
-        walk<T, STATS, false>(nodes, M, spts, me, q, lane, rec.node + 1,
-                              (int)(rec.nd & kNextMask), (int)(rec.nd >> kNextBits) + 1, rec.mask,
-                              0, nullptr, dummy, fx, fy, z, c);
+        walk<T, MET, STATS, false>(nodes, M, spts, me, q, lane, rec.node + 1,
+                                   (int)(rec.nd & kNextMask), (int)(rec.nd >> kNextBits) + 1,
+                                   rec.mask, 0, nullptr, dummy, fx, fy, z, c);
         if (valid) {
             T *o = part + (i * kWave + lane) * 2;
             o[0] = fx;
@@ -382,12 +372,15 @@ __global__ __launch_bounds__(kBlock) void k_bh_zjob(const double *__restrict__ z
     }
 }
 
-// ... then g_i = 4 (a F_attr,i - F_rep,i / Z) scattered to input order
+// ... then g_i = 4 (a F_attr,i - F_rep,i / Z) scattered to input order; with
+// `accumulate`, grad_i + scale g_i is stored instead (the second term of a sum
+// of gradients)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bh_finalize(
     const T *__restrict__ fattr, const T *__restrict__ frep, const double *__restrict__ zjob,
     const int32_t *__restrict__ pjob, const uint32_t *__restrict__ perm, int64_t n, double ex,
-    const double *__restrict__ ex_job, T *__restrict__ grad, uint32_t *__restrict__ err) {
+    const double *__restrict__ ex_job, bool accumulate, double scale, T *__restrict__ grad,
+    uint32_t *__restrict__ err) {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= n) return;
     // sorted positions of a job cover the same range as its input points
@@ -395,19 +388,24 @@ __global__ __launch_bounds__(kBlock) void k_bh_finalize(
     const double a = ex_job ? ex_job[job] : ex;
     const uint32_t i = perm[q];
     const double inv = 1.0 / zjob[job];
-    const double gx = 4.0 * (a * (double)fattr[2 * (int64_t)i] - (double)frep[2 * q] * inv);
-    const double gy = 4.0 * (a * (double)fattr[2 * (int64_t)i + 1] - (double)frep[2 * q + 1] * inv);
+    double gx = 4.0 * (a * (double)fattr[2 * (int64_t)i] - (double)frep[2 * q] * inv);
+    double gy = 4.0 * (a * (double)fattr[2 * (int64_t)i + 1] - (double)frep[2 * q + 1] * inv);
+    if (accumulate) {
+        gx = (double)grad[2 * (int64_t)i] + scale * gx;
+        gy = (double)grad[2 * (int64_t)i + 1] + scale * gy;
+    }
     const T ox = (T)gx, oy = (T)gy;
     if (!isfinite(ox) || !isfinite(oy)) atomicOr(err, HTS_ERR_NONFINITE_GRAD);
     grad[2 * (int64_t)i] = ox;
     grad[2 * (int64_t)i + 1] = oy;
 }
 
-template <typename T>
+template <typename T, int MET>
 hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n,
                                const PointRec<T> *pts, const int64_t *rp, const int32_t *col,
-                               const T *val, T *fattr, double ex, const double *ex_job, T *grad,
-                               double *z_dev, uint64_t *stats) {
+                               const T *val, T *fattr, double ex, const double *ex_job,
+                               bool accumulate, double scale, T *grad, double *z_dev,
+                               uint64_t *stats) {
     const int64_t nqb = t->nqb;
     const Jobs jb = jobs_of(t);
     const int64_t slots = nqb * kItemCap;
@@ -444,7 +442,7 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     ItemRec *dense = (ItemRec *)(base + off[10]);
     double *zjob = (double *)(base + off[11]);
 
-    const NodeRec<T> *nodes = (const NodeRec<T> *)t->nodes;
+    const NodeRec<T> *nodes = (const NodeRec<T> *)(MET == 0 ? t->nodes : t->enodes);
     const PointRec<T> *spts = (const PointRec<T> *)t->spts;
     const dim3 gq(cdiv(nqb, kBlock / kWave));
     int64_t gi = cdiv(slots, kBlock / kWave);
@@ -455,12 +453,12 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
         const int64_t top_blocks = gq.x;
         const dim3 ga(top_blocks + cdiv(n * kAttractLanes, kBlock));
         if (stats)
-            hipLaunchKernelGGL((k_bh_top<T, true>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
+            hipLaunchKernelGGL((k_bh_top<T, MET, true>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
                                st_top, dense_count, dense, top_blocks, pts, rp, col, val, n, fattr,
                                ctx->d_err);
         else
-            hipLaunchKernelGGL((k_bh_top<T, false>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
+            hipLaunchKernelGGL((k_bh_top<T, MET, false>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
                                nullptr, dense_count, dense, top_blocks, pts, rp, col, val, n,
                                fattr, ctx->d_err);
@@ -468,10 +466,10 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     {
         TimedScope ts(ctx, st, HTS_K_ITEMS);
         if (stats)
-            hipLaunchKernelGGL((k_bh_items<T, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
+            hipLaunchKernelGGL((k_bh_items<T, MET, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
                                spts, dense_count, dense, part, zitem, st_items);
         else
-            hipLaunchKernelGGL((k_bh_items<T, false>), dim3(gi), dim3(kBlock), 0, st, nodes,
+            hipLaunchKernelGGL((k_bh_items<T, MET, false>), dim3(gi), dim3(kBlock), 0, st, nodes,
                                t->d_m, spts, dense_count, dense, part, zitem, nullptr);
     }
     HTS_HIP(hipGetLastError());
@@ -485,18 +483,31 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
                            zitem, item_base, nitems, jb, nqb, frep, zq, nullptr, nullptr, nullptr);
     hipLaunchKernelGGL(k_bh_zjob, dim3(t->J), dim3(kBlock), 0, st, zq, jb, zjob, z_dev);
     hipLaunchKernelGGL(k_bh_finalize<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,
-                       zjob, t->pjob, t->perm, n, ex, ex_job, grad, ctx->d_err);
+                       zjob, t->pjob, t->perm, n, ex, ex_job, accumulate, scale, grad,
+                       ctx->d_err);
     HTS_HIP(hipGetLastError());
     return HTS_OK;
 }
 
-template hts_status launch_bh_repulsion<float>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                               const PointRec<float> *, const int64_t *,
-                                               const int32_t *, const float *, float *, double,
-                                               const double *, float *, double *, uint64_t *);
-template hts_status launch_bh_repulsion<double>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                                const PointRec<double> *, const int64_t *,
-                                                const int32_t *, const double *, double *, double,
-                                                const double *, double *, double *, uint64_t *);
+template hts_status launch_bh_repulsion<float, 0>(hts_ctx, hipStream_t, hts_tree, int64_t,
+                                                   const PointRec<float> *, const int64_t *,
+                                                   const int32_t *, const float *, float *, double,
+                                                   const double *, bool, double, float *, double *,
+                                                   uint64_t *);
+template hts_status launch_bh_repulsion<float, 1>(hts_ctx, hipStream_t, hts_tree, int64_t,
+                                                   const PointRec<float> *, const int64_t *,
+                                                   const int32_t *, const float *, float *, double,
+                                                   const double *, bool, double, float *, double *,
+                                                   uint64_t *);
+template hts_status launch_bh_repulsion<double, 0>(hts_ctx, hipStream_t, hts_tree, int64_t,
+                                                   const PointRec<double> *, const int64_t *,
+                                                   const int32_t *, const double *, double *, double,
+                                                   const double *, bool, double, double *, double *,
+                                                   uint64_t *);
+template hts_status launch_bh_repulsion<double, 1>(hts_ctx, hipStream_t, hts_tree, int64_t,
+                                                   const PointRec<double> *, const int64_t *,
+                                                   const int32_t *, const double *, double *, double,
+                                                   const double *, bool, double, double *, double *,
+                                                   uint64_t *);
 
 }  // namespace hts

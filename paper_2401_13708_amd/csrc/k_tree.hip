@@ -334,6 +334,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t *__restrict__ cnt
 }
 
 // ---------------------------------------------------------------- 6. nodes
+// radial bounds [lo, hi] of the depth-l cell holding a key (the same
+// arithmetic as the keys)
+__device__ __forceinline__ void cell_radii(uint64_t key, int l, int L,
+                                           const double *__restrict__ root, int split,
+                                           double &lo, double &hi) {
+    const int64_t job = (int64_t)(key >> (2 * L));
+    lo = root[2 * job];
+    hi = root[2 * job + 1];
+    for (int lev = 0; lev < l; ++lev) {
+        const int rb = (int)((key >> (2 * (L - 1 - lev) + 1)) & 1u);
+        const double mr = radial_mid(lo, hi, split);
+        if (rb) lo = mr; else hi = mr;
+    }
+}
+
 __device__ __forceinline__ double dd_diff(const DD3 &a, const DD3 &b, int c) {
     double s, e;
     two_sum(a.hi[c], -b.hi[c], s, e);
@@ -435,14 +450,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
     }
     rec.c = leaf ? __longlong_as_double((long long)i) : 0.0;
     nodes[k] = rec;
-    // radial bounds of the cell (same arithmetic as the keys)
-    const int64_t job = (int64_t)(key >> (2 * L));
-    double lo = root[2 * job], hi = root[2 * job + 1];
-    for (int lev = 0; lev < l; ++lev) {
-        const int rb = (int)((key >> (2 * (L - 1 - lev) + 1)) & 1u);
-        const double mr = radial_mid(lo, hi, split);
-        if (rb) lo = mr; else hi = mr;
-    }
+    double lo, hi;
+    cell_radii(key, l, L, root, split, lo, hi);
     // hyperbolic diameter: the larger of the outer-arc chord and the
     // diagonal (the radial edge is never longer than the diagonal); the
     // angular half-width is capped at pi/2 for the two top levels
@@ -557,6 +566,178 @@ hts_status tree_thresholds(hts_ctx ctx, hipStream_t st, hts_tree t, int dtype, d
     HTS_HIP(hipGetLastError());
     return HTS_OK;
 }
+
+// ---------------------------------------------------------------- Euclidean summaries
+// For the Euclidean Student-t term of h-SNE (Sec. 3) the same tree is walked
+// with Euclidean cell summaries: the centre of mass of a cell's points (from
+// double-double prefix sums of the sorted coordinates) and the criterion
+// ediam / |y - c| < theta, tested as |y - c|^2 > (ediam / theta)^2 with the
+// Euclidean diameter ediam = max(2 r_hi s, sqrt((r_hi - r_lo)^2 + 4 r_lo r_hi s^2)),
+// s the sine of half the (capped) angular width: the larger of the outer
+// chord and the diagonal, the farthest pair of corners of a polar cell.
+
+__device__ __forceinline__ DD2 dd2_add(const DD2 &a, const DD2 &b) {
+    DD2 r;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        double s, e;
+        two_sum(a.hi[c], b.hi[c], s, e);
+        e += a.lo[c] + b.lo[c];
+        const double h = s + e;
+        r.lo[c] = e - (h - s);
+        r.hi[c] = h;
+    }
+    return r;
+}
+__device__ __forceinline__ DD2 dd2_zero() {
+    DD2 r;
+    r.hi[0] = r.hi[1] = r.lo[0] = r.lo[1] = 0.0;
+    return r;
+}
+
+// block aggregates of the sorted coordinates
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_esum(const PointRec<T> *__restrict__ spts, int64_t n,
+                                                 DD2 *__restrict__ part) {
+    __shared__ DD2 sq[kBlock];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    DD2 v = dd2_zero();
+    if (i < n) {
+        v.hi[0] = (double)spts[i].x;
+        v.hi[1] = (double)spts[i].y;
+    }
+    sq[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sq[threadIdx.x] = dd2_add(sq[threadIdx.x], sq[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sq[0];
+}
+
+// one block: exclusive scan of the block aggregates in place
+__global__ __launch_bounds__(kBlock) void k_escan_parts(DD2 *__restrict__ part, int64_t nb) {
+    __shared__ DD2 sq[kBlock];
+    const int64_t per = cdiv(nb, kBlock);
+    const int64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+    DD2 v = dd2_zero();
+    for (int64_t b = b0; b < b1; ++b) v = dd2_add(v, part[b]);
+    sq[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const bool take = (int)threadIdx.x >= o;
+        const DD2 va = take ? sq[threadIdx.x - o] : dd2_zero();
+        __syncthreads();
+        if (take) sq[threadIdx.x] = dd2_add(va, sq[threadIdx.x]);
+        __syncthreads();
+    }
+    DD2 ex = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd2_zero();
+    for (int64_t b = b0; b < b1; ++b) {
+        const DD2 vb = part[b];
+        part[b] = ex;
+        ex = dd2_add(ex, vb);
+    }
+}
+
+// exclusive prefix sums psum[0..n] of the sorted coordinates
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_escan_apply(const PointRec<T> *__restrict__ spts,
+                                                        int64_t n, const DD2 *__restrict__ part,
+                                                        DD2 *__restrict__ psum) {
+    __shared__ DD2 sq[kBlock];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    DD2 v = dd2_zero();
+    if (i < n) {
+        v.hi[0] = (double)spts[i].x;
+        v.hi[1] = (double)spts[i].y;
+    }
+    sq[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const bool take = (int)threadIdx.x >= o;
+        const DD2 va = take ? sq[threadIdx.x - o] : dd2_zero();
+        __syncthreads();
+        if (take) sq[threadIdx.x] = dd2_add(va, sq[threadIdx.x]);
+        __syncthreads();
+    }
+    if (i < n) {
+        const DD2 ex = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd2_zero();
+        psum[i] = dd2_add(part[blockIdx.x], ex);
+        if (i == n - 1) psum[n] = dd2_add(part[blockIdx.x], sq[threadIdx.x]);
+    }
+}
+
+// one thread per node: the Euclidean record (count and links as the
+// hyperbolic record; leaves unchanged, internal nodes with their centre of
+// mass and Euclidean threshold)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emit_euclid(const NodeRec<T> *__restrict__ nodes,
+                                                        const int32_t *__restrict__ d_m,
+                                                        const int32_t *__restrict__ node_first,
+                                                        const uint64_t *__restrict__ keys, int L,
+                                                        const double *__restrict__ root, int split,
+                                                        const double *__restrict__ sinhalf,
+                                                        const DD2 *__restrict__ psum, double theta,
+                                                        NodeRec<T> *__restrict__ enodes) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= *d_m) return;
+    NodeRec<T> rec = nodes[k];
+    const uint32_t next = rec.next_depth & kNextMask;
+    if ((int64_t)next != k + 1) {
+        const int l = (int)(rec.next_depth >> kNextBits);
+        const int64_t i = node_first[k];
+        const int64_t end = i + rec.count;
+        const DD2 se = psum[end], si = psum[i];
+        double c[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            double sm, e;
+            two_sum(se.hi[a], -si.hi[a], sm, e);
+            e += se.lo[a] - si.lo[a];
+            c[a] = (sm + e) / (double)rec.count;
+        }
+        rec.mx = (T)c[0];
+        rec.my = (T)c[1];
+        rec.ib = 0.0;
+        double lo, hi;
+        cell_radii(keys[i], l, L, root, split, lo, hi);
+        const double s = sinhalf[l];
+        const double outer = 2.0 * hi * s;
+        const double dr = hi - lo;
+        const double diag = sqrt(dr * dr + 4.0 * lo * hi * s * s);
+        const double diam = fmax(outer, diag);
+        if (theta > 0.0) {
+            const double q = diam / theta;
+            rec.c = q * q;
+        } else {
+            rec.c = __builtin_inf();
+        }
+    }
+    enodes[k] = rec;
+}
+
+template <typename T>
+hts_status tree_euclid(hts_ctx ctx, hipStream_t st, hts_tree t, double theta) {
+    TimedScope ts(ctx, st, HTS_K_TREE);
+    const int64_t n = t->n;
+    const int64_t nb = cdiv(n, kBlock);
+    const PointRec<T> *spts = (const PointRec<T> *)t->spts;
+    hipLaunchKernelGGL(k_esum<T>, dim3(nb), dim3(kBlock), 0, st, spts, n, t->epart);
+    hipLaunchKernelGGL(k_escan_parts, dim3(1), dim3(kBlock), 0, st, t->epart, nb);
+    hipLaunchKernelGGL(k_escan_apply<T>, dim3(nb), dim3(kBlock), 0, st, spts, n, t->epart,
+                       t->epsum);
+    int64_t nbm = cdiv(n * (int64_t)(t->max_depth + 1) + 1, kBlock);
+    if (nbm > cdiv(t->cap_nodes, kBlock)) nbm = cdiv(t->cap_nodes, kBlock);
+    hipLaunchKernelGGL(k_emit_euclid<T>, dim3(nbm), dim3(kBlock), 0, st,
+                       (const NodeRec<T> *)t->nodes, t->d_m, t->node_first, t->keys, t->max_depth,
+                       t->root, t->split_rule, t->sinhalf, t->epsum, theta,
+                       (NodeRec<T> *)t->enodes);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
+template hts_status tree_euclid<float>(hts_ctx, hipStream_t, hts_tree, double);
+template hts_status tree_euclid<double>(hts_ctx, hipStream_t, hts_tree, double);
 
 template hts_status tree_build<float>(hts_ctx, hipStream_t, const float *, int64_t, hts_tree);
 template hts_status tree_build<double>(hts_ctx, hipStream_t, const double *, int64_t, hts_tree);

@@ -46,6 +46,8 @@ _SIGS = {
     "hts_tree_export": (C.c_int, [_P, _P, _P, C.POINTER(_I64), _I64, _P, _P, _P, _P, _P, _P, _P]),
     "hts_gradient_exact": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _P]),
     "hts_gradient_bh": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _D, _P, _P, _P]),
+    "hts_gradient_hsne": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _D, _P, _D, _P, _P,
+                                    _P]),
     "hts_step": (C.c_int, [_P, _P, _P, _P, _P, _P, _I64, _I32, _D, _D, _D, _D, _I32]),
     "hts_tree_set_jobs": (C.c_int, [_P, _I32, C.POINTER(_I64)]),
     "hts_gradient_bh_jobs": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _D, _P, _P,
@@ -272,6 +274,28 @@ def gradient_bh(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, theta: flo
     _ck(lib().hts_gradient_bh(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
                               _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), float(exaggeration),
                               tree.h, float(theta), _ptr(grad), _ptr(z), _ptr(stats)))
+    return grad, z
+
+
+def gradient_hsne(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, lam: float,
+                  theta: float = 0.5, exaggeration: float = 1.0, grad=None, z=None, stats=None,
+                  stream=None):
+    """h-SNE gradient (Sec. 3): the Euclidean Student-t gradient of the disk
+    coordinates plus lam times the hyperbolic one, both Barnes-Hut over the
+    tree.  z (device float64[2]) receives Z^E and Z^H; stats, if given, holds
+    20 int64 counters (Euclidean traversal, then hyperbolic)."""
+    _dev(Y, "Y")
+    _csr_args(Y, row_ptr, col_idx, p_val)
+    grad = torch.empty_like(Y) if grad is None else grad
+    z = torch.empty(2, dtype=torch.float64, device=Y.device) if z is None else z
+    if stats is not None:
+        _dev(stats, "stats", torch.int64)
+        if stats.numel() < 20:
+            raise ValueError("stats needs 20 int64 entries")
+    _ck(lib().hts_gradient_hsne(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
+                                _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), float(exaggeration),
+                                float(lam), tree.h, float(theta), _ptr(grad), _ptr(z),
+                                _ptr(stats)))
     return grad, z
 
 

@@ -1,0 +1,197 @@
+"""h-SNE gradient (Sec. 3) on the GPU against the FP64 oracle on shared seeded
+inputs: the Euclidean Student-t part of the disk coordinates over the polar
+quadtree (centres of mass, Euclidean criterion) plus lambda times the
+hyperbolic part.
+
+Bars as for the hyperbolic gradient: double precision within 1e-10 (rounding
+order only) with the traversal counters equal to the oracle's; single
+precision relative L2 <= 1e-3 against the oracle's Barnes-Hut at the same
+theta, Z relative <= 1e-5.  At the headline size (N = 70000, single
+precision) the whole result is compared."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2401_13708_amd import hts, synth
+from gpu_inputs import STAGES, affinities, embedding, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run(ctx, Y, rp, col, val, ex, lam, theta, max_depth=20, stats=False):
+    Yd = _dev(Y)
+    tree = hts.Tree(ctx, Y.shape[0], max_depth)
+    hts.build_polar_tree(ctx, Yd, tree)
+    st = torch.zeros(20, dtype=torch.int64, device="cuda") if stats else None
+    g, z = hts.gradient_hsne(ctx, Yd, _dev(rp), _dev(col), _dev(val), tree, lam, theta, ex,
+                             stats=st)
+    torch.cuda.synchronize()
+    assert ctx.check() == 0
+    tree.close()
+    out = (g.cpu().numpy(), z.cpu().numpy())
+    if stats:
+        out = out + (st.cpu().numpy().tolist(),)
+    return out
+
+
+def _oracle(Y, rp, col, val, ex, lam, theta, max_depth=20):
+    Yo = Y.astype(np.float64)
+    t = oracle.Tree(Yo, max_depth)
+    ge, ze, ce = oracle.gradient_euclid_bh(Yo, rp, col, val.astype(np.float64), t, theta, ex)
+    gh, zh, ch = oracle.gradient_bh(Yo, rp, col, val.astype(np.float64), t, theta, ex)
+    return ge + lam * gh, ze, zh, ce, ch
+
+
+@pytest.mark.parametrize("stage", STAGES)
+@pytest.mark.parametrize("theta", [0.0, 0.5])
+def test_hsne_f64_matches_oracle(ctx, stage, theta):
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, stage, np.float64)
+    g, z, st = _run(ctx, Y, rp, col, val, 12.0, 0.7, theta, stats=True)
+    go, ze, zh, ce, ch = _oracle(Y, rp, col, val, 12.0, 0.7, theta)
+    assert st[:3] == [ce["tests"], ce["accepts"], ce["pairs"]]
+    assert st[10:13] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    if theta > 0:
+        assert ce["accepts"] > 0
+    assert rel(g, go) < 1e-10
+    assert z[0] == pytest.approx(ze, rel=1e-10)
+    assert z[1] == pytest.approx(zh, rel=1e-10)
+
+
+@pytest.mark.parametrize("stage", STAGES)
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.8])
+def test_hsne_f32_matches_oracle(ctx, stage, theta):
+    n = 1337
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, stage, np.float32)
+    v32 = val.astype(np.float32)
+    g, z = _run(ctx, Y, rp, col, v32, 12.0, 1.5, theta)
+    go, ze, zh, _, _ = _oracle(Y, rp, col, v32, 12.0, 1.5, theta)
+    assert rel(g, go) < 1e-3
+    assert z[0] == pytest.approx(ze, rel=1e-5)
+    assert z[1] == pytest.approx(zh, rel=1e-5)
+
+
+@pytest.mark.parametrize("n", [2, 3, 65, 257])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_hsne_small_sizes(ctx, n, dtype):
+    X, _, rp, col, val = affinities(n, d=4, k=min(90, n - 1))
+    Y = embedding(n, "mid", dtype)
+    v = val.astype(dtype)
+    g, z = _run(ctx, Y, rp, col, v, 1.0, 0.5, 0.5)
+    go, ze, zh, _, _ = _oracle(Y, rp, col, v, 1.0, 0.5, 0.5)
+    if n == 2:
+        # p = q = 1/2 under both kernels: attraction and repulsion cancel
+        assert np.abs(g).max() < (1e-6 if dtype == np.float32 else 1e-14)
+        assert np.abs(go).max() < 1e-14
+    else:
+        assert rel(g, go) < (1e-4 if dtype == np.float32 else 1e-10)
+    tol = 1e-5 if dtype == np.float32 else 1e-12
+    assert z[0] == pytest.approx(ze, rel=tol)
+    assert z[1] == pytest.approx(zh, rel=tol)
+
+
+def test_hsne_lambda_zero_is_the_euclidean_part(ctx):
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, "late", np.float64)
+    g, z = _run(ctx, Y, rp, col, val, 4.0, 0.0, 0.5)
+    Yo = Y.astype(np.float64)
+    ge, ze, _ = oracle.gradient_euclid_bh(Yo, rp, col, val, oracle.Tree(Yo), 0.5, 4.0)
+    assert rel(g, ge) < 1e-10
+    assert z[0] == pytest.approx(ze, rel=1e-10)
+
+
+def test_hsne_hyperbolic_part_is_the_bh_gradient(ctx):
+    # g(lambda) - g(0) = lambda g^H, g^H from the hyperbolic entry point
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, "mid", np.float64)
+    g2, z2 = _run(ctx, Y, rp, col, val, 1.0, 2.0, 0.5)
+    g0, _ = _run(ctx, Y, rp, col, val, 1.0, 0.0, 0.5)
+    Yd = _dev(Y)
+    t = hts.Tree(ctx, 1000, 20)
+    hts.build_polar_tree(ctx, Yd, t)
+    gh, zh = hts.gradient_bh(ctx, Yd, _dev(rp), _dev(col), _dev(val), t, 0.5, 1.0)
+    torch.cuda.synchronize()
+    t.close()
+    assert rel(g2 - g0, 2.0 * gh.cpu().numpy()) < 1e-12
+    assert z2[1] == float(zh.cpu()[0])
+
+
+def test_hsne_duplicates_and_depth_cap(ctx):
+    n = 600
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, "late", np.float64)
+    Y[10:40] = Y[5]        # 31 identical points share one deepest leaf
+    Y[100] = Y[101]
+    for depth in (20, 6):
+        for theta in (0.0, 0.5):
+            g, z = _run(ctx, Y, rp, col, val, 1.0, 0.8, theta, max_depth=depth)
+            go, ze, zh, _, _ = _oracle(Y, rp, col, val, 1.0, 0.8, theta, max_depth=depth)
+            assert rel(g, go) < 1e-10
+            assert z[0] == pytest.approx(ze, rel=1e-10)
+
+
+def test_hsne_is_deterministic(ctx):
+    n = 1337
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, "mid", np.float32)
+    a = _run(ctx, Y, rp, col, val.astype(np.float32), 1.0, 1.0, 0.5)
+    b = _run(ctx, Y, rp, col, val.astype(np.float32), 1.0, 1.0, 0.5)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_hsne_after_hyperbolic_call_on_the_same_tree(ctx):
+    # the hyperbolic entry point between two h-SNE calls leaves them equal
+    n = 900
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, "mid", np.float32)
+    v = val.astype(np.float32)
+    Yd = _dev(Y)
+    t = hts.Tree(ctx, n, 20)
+    hts.build_polar_tree(ctx, Yd, t)
+    a, za = hts.gradient_hsne(ctx, Yd, _dev(rp), _dev(col), _dev(v), t, 0.5, 0.5)
+    a = a.cpu().numpy()
+    hts.gradient_bh(ctx, Yd, _dev(rp), _dev(col), _dev(v), t, 0.8)
+    b, zb = hts.gradient_hsne(ctx, Yd, _dev(rp), _dev(col), _dev(v), t, 0.5, 0.5)
+    torch.cuda.synchronize()
+    t.close()
+    assert np.array_equal(a, b.cpu().numpy())
+
+
+def test_hsne_argument_errors(ctx):
+    n = 300
+    X, _, rp, col, val = affinities(n)
+    Y = _dev(embedding(n, "mid", np.float32))
+    t = hts.Tree(ctx, n, 20)
+    hts.build_polar_tree(ctx, Y, t)
+    args = (_dev(rp), _dev(col), _dev(val.astype(np.float32)))
+    for lam in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(hts.HTSError):
+            hts.gradient_hsne(ctx, Y, *args, t, lam, 0.5)
+    with pytest.raises(hts.HTSError):
+        hts.gradient_hsne(ctx, Y, *args, t, 1.0, -0.1)
+    t.close()
+    t2 = hts.Tree(ctx, n, 20)
+    t2.set_jobs([100, 200])
+    hts.build_polar_tree(ctx, Y, t2)
+    with pytest.raises(hts.HTSError):
+        hts.gradient_hsne(ctx, Y, *args, t2, 1.0, 0.5)
+    t2.close()
+    assert ctx.check() == 0
+
+
+@pytest.mark.parametrize("stage", ["mid", "edge"])
+def test_hsne_headline_size(ctx, stage):
+    n = 70000
+    Y = embedding(n, stage, np.float32)
+    rp, col, v32 = synth.random_csr(n, 90, seed=13, dtype=np.float32)
+    g, z = _run(ctx, Y, rp, col, v32, 12.0, 1.0, 0.5)
+    go, ze, zh, _, _ = _oracle(Y, rp, col, v32, 12.0, 1.0, 0.5)
+    assert rel(g, go) < 1e-3
+    assert z[0] == pytest.approx(ze, rel=1e-5)
+    assert z[1] == pytest.approx(zh, rel=1e-5)
