@@ -31,6 +31,11 @@ VALU_PEAK_TFLOPS = 78.6
 # (accepted cell or leaf point) adds sinh d, d, w, the force factor, the
 # direction vector and the three accumulations (26 flops).
 F_TEST, F_PAIR = 9, 26
+# The Euclidean traversal of the h-SNE term: a test forms |y-c|^2 and
+# compares (6 flops); an interaction adds w = 1/(1+|y-c|^2), N w^2, the
+# direction vector and the three accumulations (12 flops).
+F_TEST_E, F_PAIR_E = 6, 12
+METRIC_HSNE = "h-SNE BH gradient iters/sec at N=70k θ=0.5 (Euclidean + λ hyperbolic term)"
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
@@ -61,7 +66,7 @@ def _traffic(kernel):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(n, seconds, theta):
+def cpu_baseline(n, seconds, theta, hsne_lambda=None):
     import numpy as np
     import oracle
     from paper_2401_13708_amd import synth
@@ -74,18 +79,23 @@ def cpu_baseline(n, seconds, theta):
     t0 = time.perf_counter()
     while True:
         t = oracle.Tree(Y)
-        g, z, _ = oracle.gradient_bh(Y, rp, col, val, t, theta, 12.0)
+        if hsne_lambda is None:
+            g, z, _ = oracle.gradient_bh(Y, rp, col, val, t, theta, 12.0)
+        else:
+            g, _, _ = oracle.hsne_gradient_bh(Y, rp, col, val, t, theta, hsne_lambda, 12.0)
         Y, U, G = oracle.step(Y, U, G, g, n / 12000.0, 0.5)
         del t
         it += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
+    what = "Barnes-Hut gradient" if hsne_lambda is None else \
+        "h-SNE Barnes-Hut gradient (Euclidean + %g x hyperbolic)" % hsne_lambda
     return {"value": it / el, "unit": "iters/s", "cores": cores, "kind": "oracle",
-            "sample": "%d full iterations (polar quadtree by insertion + Barnes-Hut gradient at "
+            "sample": "%d full iterations (polar quadtree by insertion + %s at "
                       "theta=%.1f + step) of the FP64 oracle at N=%d on a synthetic clustered "
                       "embedding with a k-NN-shaped random P (nnz=%d), %.1f s, OpenMP over "
-                      "queries" % (it, theta, n, int(rp[-1]), el)}
+                      "queries" % (it, what, theta, n, int(rp[-1]), el)}
 
 
 def _job_set(ctx, dev, count, seed, n_lo, n_hi, dims, iters_note=""):
@@ -279,6 +289,8 @@ def main():
                     help="also run a plain device copy of this size (for PMC calibration)")
     ap.add_argument("--split-rule", type=int, choices=[0, 1], default=0,
                     help="radial split: 0 equal lengths (eq. (10)), 1 equal areas (eq. (9))")
+    ap.add_argument("--hsne-lambda", type=float, default=None,
+                    help="time the h-SNE iteration (Euclidean + lambda x hyperbolic term) instead")
     ap.add_argument("--workload", choices=["single", "jobs", "serve"], default="single",
                     help="single: the N=70k iteration (default); jobs: 64 uneven jobs batched; "
                          "serve: Poisson arrivals through the continuous-batching server")
@@ -325,11 +337,16 @@ def main():
     print("bench: affinities nnz=%d in %.2fs" % (nnz, aff_s), file=sys.stderr, flush=True)
 
     Y0d = torch.from_numpy(Y0).to(dev)
+    hs = args.hsne_lambda
+    if hs is not None and hs < 0:
+        raise SystemExit("bench.py: --hsne-lambda must be >= 0")
+    nst = 10 if hs is None else 20
 
     def run_pass(events, stats):
         """Warm-up + the timed iterations from the same start; the iteration
         is deterministic, so every pass follows the same trajectory."""
-        emb = Embedding(ctx, rp, col, val, Y0d, theta=args.theta, split_rule=args.split_rule)
+        emb = Embedding(ctx, rp, col, val, Y0d, theta=args.theta, split_rule=args.split_rule,
+                        hsne_lambda=hs)
         for _ in range(args.warmup):
             emb.iterate()
         torch.cuda.synchronize()
@@ -367,9 +384,9 @@ def main():
         print("bench: kernel events %s" % {k: round(v[0] / args.steps, 4) for k, v in kt.items() if v[1]},
               file=sys.stderr, flush=True)
     # pass 3: traversal counters (the kernels' counting variants)
-    st = [0] * 10
+    st = [0] * nst
     if not args.no_stats:
-        stats = torch.zeros(10, dtype=torch.int64, device=dev)
+        stats = torch.zeros(nst, dtype=torch.int64, device=dev)
         e3, _, _, _ = run_pass(False, stats)
         e3.close()
         st = stats.cpu().numpy().tolist()
@@ -377,7 +394,7 @@ def main():
 
     # exact O(N^2) gradient + step at the same N, from the same state
     exact_ips = None
-    if args.exact_steps > 0:
+    if args.exact_steps > 0 and hs is None:
         ex = Embedding(ctx, rp, col, val, emb.Y, exact=True)
         ex.update.copy_(emb.update)
         ex.gains.copy_(emb.gains)
@@ -414,8 +431,15 @@ def main():
     if launches.get(dom, 0) > 0:
         avg_s = kms[dom] / launches[dom] / 1000.0
         if dom in ("traverse", "items"):
-            share = st[5:10] if dom == "items" else [a - b for a, b in zip(st[:5], st[5:10])]
-            flops = (share[0] * F_TEST + (share[1] + share[2]) * F_PAIR) / launches[dom]
+            def part(c):  # the kernel's share of one traversal's counters
+                return c[5:10] if dom == "items" else [a - b for a, b in zip(c[:5], c[5:10])]
+            if hs is None:
+                share = part(st[:10])
+                flops = (share[0] * F_TEST + (share[1] + share[2]) * F_PAIR) / launches[dom]
+            else:  # two launches per iteration: the Euclidean walk, then the hyperbolic one
+                se, sh = part(st[:10]), part(st[10:20])
+                flops = (se[0] * F_TEST_E + (se[1] + se[2]) * F_PAIR_E + sh[0] * F_TEST
+                         + (sh[1] + sh[2]) * F_PAIR) / launches[dom]
             ach = flops / avg_s / 1e12
             roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),
@@ -437,10 +461,20 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle for ~%.0fs" % args.cpu_seconds, file=sys.stderr, flush=True)
-        cpu = cpu_baseline(n, args.cpu_seconds, args.theta)
+        cpu = cpu_baseline(n, args.cpu_seconds, args.theta, hs)
 
+    def counts(c):
+        return {"tests": c[0] // max(1, args.steps),
+                "accepted_cells": c[1] // max(1, args.steps),
+                "leaf_pairs": c[2] // max(1, args.steps),
+                "wave_node_visits": c[3] // max(1, args.steps),
+                "wave_visits_with_work": c[4] // max(1, args.steps),
+                "share_of_item_walks": [round(b / a, 3) if a else 0.0 for a, b in zip(c[:5], c[5:10])]}
+
+    workload = ("hyperbolic t-SNE Barnes-Hut iteration" if hs is None else
+                "h-SNE Barnes-Hut iteration (Euclidean term + %g x hyperbolic term)" % hs)
     out = {
-        "metric": METRIC,
+        "metric": METRIC if hs is None else METRIC_HSNE,
         "value": round(value, 2),
         "unit": "iters/s",
         "n_gpus": 1,
@@ -452,23 +486,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "hyperbolic t-SNE Barnes-Hut iteration, N=%d D=%d sigmoid factor "
+        "config": {"workload": "%s, N=%d D=%d sigmoid factor "
                                "mixture, perplexity 30, k=90, theta=%.2f, iterations %d-%d of the "
-                               "1000-iteration schedule" % (n, d, args.theta, args.warmup,
+                               "1000-iteration schedule" % (workload, n, d, args.theta, args.warmup,
                                                             args.warmup + args.steps - 1),
                    "n": n, "d": d, "theta": args.theta, "perplexity": 30, "k": 90, "nnz": nnz,
                    "split_rule": "equal lengths, eq. (10)" if args.split_rule == 0
-                   else "equal areas, eq. (9)"},
+                   else "equal areas, eq. (9)", "hsne_lambda": hs},
         "exact_iters_per_s": round(exact_ips, 3) if exact_ips else None,
         "speedup_vs_exact": round(value / exact_ips, 1) if exact_ips else None,
         "kernel_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kt.items() if v[1]},
-        "bh_counts_per_step": {"tests": st[0] // max(1, args.steps),
-                               "accepted_cells": st[1] // max(1, args.steps),
-                               "leaf_pairs": st[2] // max(1, args.steps),
-                               "wave_node_visits": st[3] // max(1, args.steps),
-                               "wave_visits_with_work": st[4] // max(1, args.steps),
-                               "share_of_item_walks": [round(b / a, 3) if a else 0.0
-                                                       for a, b in zip(st[:5], st[5:10])]},
+        "bh_counts_per_step": counts(st[:10]) if hs is None else
+        {"euclidean": counts(st[:10]), "hyperbolic": counts(st[10:20])},
         "setup_s": {"generate": round(gen_s, 2), "affinities_gpu": round(aff_s, 3)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -42,14 +42,20 @@ class Embedding:
 
     def __init__(self, ctx: hts.Context, row_ptr, col_idx, p_val, Y0, theta: float = 0.5,
                  exact: bool = False, max_depth: int = 20, schedule: Schedule | None = None,
-                 split_rule: int = 0):
+                 split_rule: int = 0, hsne_lambda: float | None = None):
         self.ctx = ctx
         self.rp, self.col, self.val = row_ptr, col_idx, p_val
         self.Y = Y0.clone()
         self.update = torch.zeros_like(self.Y)
         self.gains = torch.ones_like(self.Y)
         self.grad = torch.empty_like(self.Y)
-        self.z = torch.zeros(1, dtype=torch.float64, device=self.Y.device)
+        # h-SNE (Sec. 3): Euclidean term plus hsne_lambda times the hyperbolic
+        # one (Barnes-Hut only); z then holds Z^E and Z^H
+        self.hsne_lambda = hsne_lambda
+        if hsne_lambda is not None and exact:
+            raise ValueError("the h-SNE gradient is Barnes-Hut only")
+        self.z = torch.zeros(1 if hsne_lambda is None else 2, dtype=torch.float64,
+                             device=self.Y.device)
         self.n = self.Y.shape[0]
         self.theta = theta
         self.exact = exact
@@ -65,8 +71,12 @@ class Embedding:
             hts.gradient_exact(self.ctx, self.Y, self.rp, self.col, self.val, ex, self.grad, self.z)
         else:
             hts.build_polar_tree(self.ctx, self.Y, self.tree)
-            hts.gradient_bh(self.ctx, self.Y, self.rp, self.col, self.val, self.tree, self.theta, ex,
-                            self.grad, self.z, stats)
+            if self.hsne_lambda is None:
+                hts.gradient_bh(self.ctx, self.Y, self.rp, self.col, self.val, self.tree,
+                                self.theta, ex, self.grad, self.z, stats)
+            else:
+                hts.gradient_hsne(self.ctx, self.Y, self.rp, self.col, self.val, self.tree,
+                                  self.hsne_lambda, self.theta, ex, self.grad, self.z, stats)
         s = self.sched
         hts.step(self.ctx, self.Y, self.update, self.gains, self.grad, eta, mu, s.min_gain,
                  s.boundary_eps, s.metric_power)

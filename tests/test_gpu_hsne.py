@@ -195,3 +195,31 @@ def test_hsne_headline_size(ctx, stage):
     assert rel(g, go) < 1e-3
     assert z[0] == pytest.approx(ze, rel=1e-5)
     assert z[1] == pytest.approx(zh, rel=1e-5)
+
+
+@pytest.mark.parametrize("lam", [None, 0.5])
+def test_driver_iterations_match_oracle(ctx, lam):
+    # whole iterations through the driver (tree, gradient, step, the schedule
+    # of Sec. 5) against the same loop over the oracle, in double precision;
+    # lam None is the hyperbolic iteration, otherwise h-SNE
+    from paper_2401_13708_amd.embed import Embedding, Schedule
+    n = 600
+    X, _, rp, col, val = affinities(n)
+    Y0 = synth.disk_uniform(n, 1e-4, seed=17, dtype=np.float64)
+    e = Embedding(ctx, _dev(rp), _dev(col), _dev(val), _dev(Y0), hsne_lambda=lam)
+    e.run(6)
+    torch.cuda.synchronize()
+    assert ctx.check() == 0
+    Yg = e.Y.cpu().numpy()
+    e.close()
+    Y, U, G = Y0.copy(), np.zeros_like(Y0), np.ones_like(Y0)
+    sch = Schedule()
+    for it in range(6):
+        ex, mu, eta = sch.at(it, n)
+        t = oracle.Tree(Y)
+        if lam is None:
+            g, _, _ = oracle.gradient_bh(Y, rp, col, val, t, 0.5, ex)
+        else:
+            g, _, _ = oracle.hsne_gradient_bh(Y, rp, col, val, t, 0.5, lam, ex)
+        Y, U, G = oracle.step(Y, U, G, g, eta, mu)
+    assert rel(Yg, Y) < 1e-9
