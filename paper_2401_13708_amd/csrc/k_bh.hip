@@ -34,7 +34,9 @@ namespace hts {
 
 constexpr int kStats = 5;
 constexpr int kAttractLanes = 16;  // lanes per CSR row of the attractive term
-constexpr int kItemCap = 256;  // items one query block can hand to phase B
+constexpr int kItemCap = 256;  // items one phase-A wave can hand to phase B
+constexpr int kTopDepth = 1;   // phase A splits each query block's walk at this depth ...
+constexpr int kTopSlots = 1 << (2 * kTopDepth);  // ... over this many waves
 
 // work item as phase A records it (in LDS) ...
 struct LdsItem {
@@ -156,10 +158,19 @@ __device__ __forceinline__ void put_stats(uint32_t *__restrict__ sp, const Count
     sp[4] = (uint32_t)c.work;
 }
 
-// Phase A: one wave per query block over the nodes of more than S points.
-// These few waves are latency-bound and leave most of the chip idle, so the
-// same launch also carries the attractive term (first sum of eq. (15)), which
-// streams P: workgroups from top_blocks on compute its rows.
+// Phase A: the walk of a query block over the nodes of more than S points,
+// split over kTopSlots = 4^kTopDepth waves.  Slot s owns one node f of the
+// frontier at depth kTopDepth (its base-4 digits pick the child at each level
+// below the root; a leaf above that depth belongs to the slot whose remaining
+// digits are 0; a slot naming a missing child is idle).  The wave first tests
+// the ancestors of f for its lanes -- a lane that accepts one, or whose
+// rejected ancestor becomes a work item, leaves the walk -- then walks f's
+// subtree.  An ancestor's term, item and counters belong to the one slot whose
+// digits below it are all 0, so every lane meets every cell exactly as in a
+// single depth-first walk.  These waves are latency-bound chains and leave
+// most of the chip idle, so the same launch also carries the attractive term
+// (first sum of eq. (15)), which streams P: workgroups from top_blocks on
+// compute its rows.
 template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_top(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
@@ -176,7 +187,9 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
                                             n, fattr, err);
         return;
     }
-    const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t g = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t qb = g / kTopSlots;
+    const int slot = (int)(g % kTopSlots);
     if (qb >= nqb) return;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     LdsItem *items = s_items[threadIdx.x / kWave];
@@ -190,17 +203,69 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     const bool valid = lane < cnt;
     const PointRec<T> me = spts[valid ? q : q0];
     const int M = uniform(*d_m);
-    // the job's tree: the pre-order range from its root to the next job's
-    const int k0 = uniform(node_start[jb.off[job]]);
-    const int k1 = uniform(node_start[jb.off[job + 1]]);
+    // the job's tree: the pre-order range from its root
+    int a = uniform(node_start[jb.off[job]]);
     T fx = 0, fy = 0;
     double z = 0.0;
     Counters c;
     int nitems = 0;
-    walk<T, MET, STATS, true>(nodes, M, spts, me, q, lane, k0, k1, 0, __ballot(valid), S, items,
-                               nitems, fx, fy, z, c);
-    // reserve a contiguous run of the item list (one atomic per block; the
-    // runs of different blocks may come in any order)
+    uint64_t m = __ballot(valid);
+    bool live = true;
+    for (int d = 0; d < kTopDepth; ++d) {
+        const NodeRec<T> A = nodes[a];
+        const uint32_t nxd = (uint32_t)uniform((int)A.next_depth);
+        const int nx = (int)(nxd & kNextMask);
+        // this slot owns node a when its digits below depth d are all 0
+        const bool owner = (slot & ((1 << (2 * (kTopDepth - d))) - 1)) == 0;
+        if (nx == a + 1) {  // a leaf above the frontier depth: its owner walks it
+            live = owner;
+            break;
+        }
+        const bool in = (m >> lane) & 1ull;
+        bool acc = false;
+        if (in) {
+            double dd;
+            const double t = Geo<MET>::arg(me, A.mx, A.my, A.ib, dd);
+            acc = t > A.c;
+            if (acc && owner) Geo<MET>::repel(me, A.mx, A.my, A.ib, t, dd, (T)A.count, fx, fy, z);
+        }
+        const uint64_t rej = __ballot(in && !acc);
+        if (STATS && owner) {
+            const uint64_t am = __ballot(acc);
+            c.test += __popcll(m);
+            c.acc += __popcll(am);
+            c.step += 1;
+            c.work += am != 0;
+        }
+        if (rej && A.count <= S) {  // the rejecting lanes take the cell as one work item
+            if (owner) {
+                if (lane == 0) items[nitems] = LdsItem{a, nxd, rej};
+                ++nitems;
+            }
+            m = 0;
+        } else {
+            m = rej;
+        }
+        if (!m) break;
+        // the child picked by this slot's digit at depth d + 1
+        const int digit = (slot >> (2 * (kTopDepth - 1 - d))) & 3;
+        int ch = a + 1;
+        for (int i = 0; i < digit && ch < nx; ++i)
+            ch = (int)((uint32_t)uniform((int)nodes[ch].next_depth) & kNextMask);
+        if (ch >= nx) {
+            live = false;
+            break;
+        }
+        a = ch;
+    }
+    if (live && m) {
+        const int nxa = (int)((uint32_t)uniform((int)nodes[a].next_depth) & kNextMask);
+        const int da = (int)((uint32_t)uniform((int)nodes[a].next_depth) >> kNextBits);
+        walk<T, MET, STATS, true>(nodes, M, spts, me, q, lane, a, nxa, da, m, S, items, nitems,
+                                   fx, fy, z, c);
+    }
+    // reserve a contiguous run of the item list (one atomic per wave; the
+    // runs of different waves may come in any order)
     int base = 0;
     if (lane == 0 && nitems > 0) base = (int)atomicAdd(dense_count, (unsigned)nitems);
     base = __shfl(base, 0, 64);
@@ -212,15 +277,15 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
         dense[base + j] = ItemRec{it.node, it.nd, (int32_t)q0, cnt, it.mask, 0};
     }
     if (valid) {
-        part0[2 * q] = fx;
-        part0[2 * q + 1] = fy;
+        part0[((int64_t)slot * n + q) * 2] = fx;
+        part0[((int64_t)slot * n + q) * 2 + 1] = fy;
     }
     const double zs = wave_sum(z);
     if (lane == 0) {
-        ztop[qb] = zs;
-        item_base[qb] = base;
-        nitems_out[qb] = nitems;
-        put_stats<STATS>(stats_top + qb * kStats, c);
+        ztop[g] = zs;
+        item_base[g] = base;
+        nitems_out[g] = nitems;
+        put_stats<STATS>(stats_top + g * kStats, c);
     }
 }
 
@@ -280,14 +345,15 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
     }
 }
 
-// Combine, stage 1: one wave per query block adds its partials in item order
-// (eight loads in flight at a time); the counters of the block are added to
-// the caller's totals.
+// Combine, stage 1: one wave per query block adds, slot by slot, the slot's
+// phase-A partial and then its items' partials in item order (eight loads in
+// flight at a time); the counters of the block are added to the caller's
+// totals.
 template <typename T, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_gather(
     const T *__restrict__ part0, const double *__restrict__ ztop, const T *__restrict__ part,
     const double *__restrict__ zitem, const int *__restrict__ item_base,
-    const int *__restrict__ nitems_in, Jobs jb, int64_t nqb, T *__restrict__ frep,
+    const int *__restrict__ nitems_in, Jobs jb, int64_t nqb, int64_t n, T *__restrict__ frep,
     double *__restrict__ zq, const uint32_t *__restrict__ stats_top,
     const uint32_t *__restrict__ stats_items, unsigned long long *__restrict__ stats) {
     const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
@@ -298,52 +364,68 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
     jb.block(qb, q0, cnt, job);
     const int64_t q = q0 + lane;
     const bool valid = lane < cnt;
-    const int64_t b0 = uniform(item_base[qb]);
-    const int ni = uniform(nitems_in[qb]);
-    T fx = valid ? part0[2 * q] : (T)0, fy = valid ? part0[2 * q + 1] : (T)0;
+    T fx = 0, fy = 0;
+    double zb = 0.0;
+    unsigned long long s_all[kStats], s_it[kStats];
+#pragma unroll
+    for (int a = 0; a < kStats; ++a) s_all[a] = s_it[a] = 0;
+    for (int sl = 0; sl < kTopSlots; ++sl) {
+        const int64_t g = qb * kTopSlots + sl;
+        const int64_t b0 = uniform(item_base[g]);
+        const int ni = uniform(nitems_in[g]);
+        if (valid) {
+            fx += part0[((int64_t)sl * n + q) * 2];
+            fy += part0[((int64_t)sl * n + q) * 2 + 1];
+            constexpr int U = 8;
+            int j = 0;
+            for (; j + U <= ni; j += U) {
+                T px[U], py[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const T *p = part + ((b0 + j + u) * kWave + lane) * 2;
+                    px[u] = p[0];
+                    py[u] = p[1];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    fx += px[u];
+                    fy += py[u];
+                }
+            }
+            for (; j < ni; ++j) {
+                const T *p = part + ((b0 + j) * kWave + lane) * 2;
+                fx += p[0];
+                fy += p[1];
+            }
+        }
+        double zl = 0.0;
+        for (int j = lane; j < ni; j += kWave) zl += zitem[b0 + j];
+        zb += ztop[g] + wave_sum(zl);
+        if (STATS) {
+            for (int j = lane; j < ni; j += kWave)
+#pragma unroll
+                for (int a = 0; a < kStats; ++a) s_it[a] += stats_items[(b0 + j) * kStats + a];
+            if (lane == 0)
+#pragma unroll
+                for (int a = 0; a < kStats; ++a) s_all[a] += stats_top[g * kStats + a];
+        }
+    }
     if (valid) {
-        constexpr int U = 8;
-        int j = 0;
-        for (; j + U <= ni; j += U) {
-            T px[U], py[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const T *p = part + ((b0 + j + u) * kWave + lane) * 2;
-                px[u] = p[0];
-                py[u] = p[1];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                fx += px[u];
-                fy += py[u];
-            }
-        }
-        for (; j < ni; ++j) {
-            const T *p = part + ((b0 + j) * kWave + lane) * 2;
-            fx += p[0];
-            fy += p[1];
-        }
         frep[2 * q] = fx;
         frep[2 * q + 1] = fy;
     }
-    double zl = 0.0;
-    for (int j = lane; j < ni; j += kWave) zl += zitem[b0 + j];
-    const double zs = wave_sum(zl);
-    if (lane == 0) zq[qb] = ztop[qb] + zs;
+    if (lane == 0) zq[qb] = zb;
     if (STATS) {
-        unsigned long long s[kStats];
-#pragma unroll
-        for (int a = 0; a < kStats; ++a) s[a] = 0;
-        for (int j = lane; j < ni; j += kWave)
-#pragma unroll
-            for (int a = 0; a < kStats; ++a) s[a] += stats_items[(b0 + j) * kStats + a];
 #pragma unroll
         for (int a = 0; a < kStats; ++a) {
-            unsigned long long v = s[a];
+            unsigned long long v = s_it[a], w = s_all[a];
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            for (int o = 32; o >= 1; o >>= 1) {
+                v += __shfl_xor(v, o, 64);
+                w += __shfl_xor(w, o, 64);
+            }
             if (lane == 0) {
-                atomicAdd(&stats[a], v + stats_top[qb * kStats + a]);
+                atomicAdd(&stats[a], v + w);
                 atomicAdd(&stats[kStats + a], v);
             }
         }
@@ -408,14 +490,15 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
                                uint64_t *stats) {
     const int64_t nqb = t->nqb;
     const Jobs jb = jobs_of(t);
-    const int64_t slots = nqb * kItemCap;
+    const int64_t nw = nqb * kTopSlots;  // phase-A waves
+    const int64_t slots = nw * kItemCap;
     const int S = ctx->item_points;
     // workspace: item list, partials, per-block sums
-    const size_t b_base = (size_t)nqb * 4, b_nit = (size_t)nqb * 4;
-    const size_t b_part0 = (size_t)n * 2 * sizeof(T), b_ztop = (size_t)nqb * 8;
+    const size_t b_base = (size_t)nw * 4, b_nit = (size_t)nw * 4;
+    const size_t b_part0 = (size_t)kTopSlots * n * 2 * sizeof(T), b_ztop = (size_t)nw * 8;
     const size_t b_part = (size_t)slots * kWave * 2 * sizeof(T), b_zitem = (size_t)slots * 8;
     const size_t b_frep = (size_t)n * 2 * sizeof(T), b_zq = (size_t)nqb * 8;
-    const size_t b_st = stats ? (size_t)(slots + nqb) * kStats * 4 : 0;
+    const size_t b_st = stats ? (size_t)(slots + nw) * kStats * 4 : 0;
     const size_t b_cnt = 256, b_dense = (size_t)slots * sizeof(ItemRec);
     const size_t b_zjob = (size_t)t->J * 8;
     constexpr int R = 12;
@@ -450,7 +533,7 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kWave), 0, st, dense_count);
     {
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
-        const int64_t top_blocks = gq.x;
+        const int64_t top_blocks = cdiv(nw, kBlock / kWave);
         const dim3 ga(top_blocks + cdiv(n * kAttractLanes, kBlock));
         if (stats)
             hipLaunchKernelGGL((k_bh_top<T, MET, true>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
@@ -476,11 +559,12 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     TimedScope ts(ctx, st, HTS_K_FINALIZE);
     if (stats)
         hipLaunchKernelGGL((k_bh_gather<T, true>), gq, dim3(kBlock), 0, st, part0, ztop, part,
-                           zitem, item_base, nitems, jb, nqb, frep, zq, st_top, st_items,
+                           zitem, item_base, nitems, jb, nqb, n, frep, zq, st_top, st_items,
                            (unsigned long long *)stats);
     else
         hipLaunchKernelGGL((k_bh_gather<T, false>), gq, dim3(kBlock), 0, st, part0, ztop, part,
-                           zitem, item_base, nitems, jb, nqb, frep, zq, nullptr, nullptr, nullptr);
+                           zitem, item_base, nitems, jb, nqb, n, frep, zq, nullptr, nullptr,
+                           nullptr);
     hipLaunchKernelGGL(k_bh_zjob, dim3(t->J), dim3(kBlock), 0, st, zq, jb, zjob, z_dev);
     hipLaunchKernelGGL(k_bh_finalize<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,
                        zjob, t->pjob, t->perm, n, ex, ex_job, accumulate, scale, grad,
