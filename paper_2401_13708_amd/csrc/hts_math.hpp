@@ -70,7 +70,11 @@ __device__ __forceinline__ PairTerm<float> pair_term<float>(float qx, float qy, 
                                                             double dd) {
     PairTerm<float> r;
     const float tf = (float)t;
-    const float sh = __builtin_amdgcn_sqrtf(tf * (tf + 2.0f));
+    // one reciprocal square root gives 1 / sinh d; sinh d from it (0 for a
+    // vanishing argument, where the reciprocal is infinite)
+    const float x = tf * (tf + 2.0f);
+    const float rs = __builtin_amdgcn_rsqf(x);
+    const float sh = x > 1e-30f ? x * rs : 0.0f;
     float qs = 16.0f / 3003.0f;
     qs = __builtin_fmaf(qs, tf, -8.0f / 693.0f);
     qs = __builtin_fmaf(qs, tf, 8.0f / 315.0f);
@@ -80,7 +84,7 @@ __device__ __forceinline__ PairTerm<float> pair_term<float>(float qx, float qy, 
     qs = __builtin_fmaf(qs, tf, 1.0f);
     const float dl = __builtin_amdgcn_logf(1.0f + tf + sh) * 0.6931471805599453f;
     const bool small = tf < 0.125f;
-    const float ratio = small ? qs : dl * __builtin_amdgcn_rcpf(sh);
+    const float ratio = small ? qs : dl * rs;
     const float d = small ? qs * sh : dl;
     r.w = __builtin_amdgcn_rcpf(__builtin_fmaf(d, d, 1.0f));
     r.base = ratio * (float)(4.0 * qia * oib);
@@ -106,15 +110,15 @@ template <> struct Geo<0> {
                                                  double &dd) {
         return dist_arg<T>(me.x, me.y, me.ia, ox, oy, oib, dd);
     }
-    template <typename T>
+    template <typename T, typename Z>
     static __device__ __forceinline__ void repel(const PointRec<T> &me, T ox, T oy, double oib,
                                                  double t, double dd, T weight, T &fx, T &fy,
-                                                 double &z) {
+                                                 Z &z) {
         const PairTerm<T> r = pair_term<T>(me.x, me.y, me.ia, ox, oy, oib, t, dd);
         const T coef = weight * r.w * r.w * r.base;
         fx += coef * r.vx;
         fy += coef * r.vy;
-        z += (double)(weight * r.w);
+        z += (Z)(weight * r.w);
     }
     template <typename T>
     static __device__ __forceinline__ T attract(const PointRec<T> &q, const PointRec<T> &o, T p,
@@ -143,17 +147,17 @@ template <> struct Geo<1> {
         dd = dx * dx + dy * dy;
         return dd;
     }
-    template <typename T>
+    template <typename T, typename Z>
     static __device__ __forceinline__ void repel(const PointRec<T> &me, T ox, T oy, double oib,
                                                  double t, double dd, T weight, T &fx, T &fy,
-                                                 double &z) {
+                                                 Z &z) {
         (void)oib;
         (void)t;
         const T w = recip<T>((T)1 + (T)dd);
         const T coef = weight * w * w;
         fx += coef * (me.x - ox);
         fy += coef * (me.y - oy);
-        z += (double)(weight * w);
+        z += (Z)(weight * w);
     }
     template <typename T>
     static __device__ __forceinline__ T attract(const PointRec<T> &q, const PointRec<T> &o, T p,

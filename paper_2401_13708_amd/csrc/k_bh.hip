@@ -70,6 +70,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                                      int64_t q, int lane, int k, int kend, int d0, uint64_t mask0,
                                      int S, LdsItem *items, int &nitems, T &fx, T &fy, double &z,
                                      Counters &c) {
+    T zw = 0;  // this walk's Z terms, added to z once at the end
     int mlo = lane == d0 ? (int)(uint32_t)mask0 : 0;
     int mhi = lane == d0 ? (int)(uint32_t)(mask0 >> 32) : 0;
     NodeRec<T> nrec = nodes[k < M ? k : M - 1];
@@ -93,7 +94,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 if (use) {
                     double dd;
                     double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
-                    Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, z);
+                    Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, zw);
                 }
                 if (STATS) {
                     const uint64_t um = __ballot(use);
@@ -107,7 +108,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                     if (use) {
                         double dd;
                         double t = Geo<MET>::arg(me, o.x, o.y, o.ia, dd);
-                        Geo<MET>::repel(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, z);
+                        Geo<MET>::repel(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, zw);
                     }
                     if (STATS) c.pair += __popcll(__ballot(use));
                 }
@@ -120,7 +121,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 double dd;
                 double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
                 acc = t > cur.c;
-                if (acc) Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, z);
+                if (acc) Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, zw);
             }
             const uint64_t rej = __ballot(in && !acc);
             if (STATS) {
@@ -146,6 +147,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             }
         }
     }
+    z += (double)zw;
 }
 
 template <bool STATS>
