@@ -155,7 +155,8 @@ hts_status hts_tree_export(hts_ctx ctx, hts_stream stream, hts_tree tree,
  * with a = exaggeration > 0.  grad (n x 2) receives this Euclidean variation
  * (no metric rescaling); *z_dev (device double) receives Z.
  * Single precision: forces in float with float accumulation; the distance
- * argument 2|yi-yj|^2 / ((1-|yi|^2)(1-|yj|^2)), the criterion and Z in double.
+ * argument 2|yi-yj|^2 / ((1-|yi|^2)(1-|yj|^2)) and the criterion in double;
+ * Z from float partial sums (one per subtree walk) added up in double.
  * ---------------------------------------------------------------------- */
 
 /* Exact O(n^2) repulsion. */
