@@ -158,8 +158,8 @@ def autotune_item_points(ctx: hts.Context, jobs: list[Job], candidates=(128, 256
     `reps` iterations from that same state.  The fastest is set on ctx and
     returned with the per-candidate milliseconds per iteration."""
     b = JobBatch(ctx, jobs, theta=theta)
-    prev = getattr(ctx, "item_points", 512)
-    ctx.set_item_points(512)
+    prev = getattr(ctx, "item_points", hts.DEFAULT_ITEM_POINTS)
+    ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
     b.run(warm)
     saved = [t.clone() for t in (b.Y, b.update, b.gains, b.it)]
     times = {}

@@ -89,7 +89,7 @@ struct Buffer {
 
 struct hts_ctx_s {
     int device = 0;
-    int32_t item_points = 512;  // Barnes-Hut work-item size S (hts_set_item_points)
+    int32_t item_points = 256;  // Barnes-Hut work-item size S (hts_set_item_points)
     uint32_t *d_err = nullptr;
     hts::Buffer pts, fattr, frep, zpart, part, spare;
     hts::Buffer aff[8];

@@ -116,13 +116,12 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             k = next;
             nrec = over;
         } else {
-            bool acc = false;
-            if (in) {
-                double dd;
-                double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
-                acc = t > cur.c;
-                if (acc) Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, zw);
-            }
+            // the test costs the same for every lane (some lane of the wave
+            // is always in the mask here); only the term is masked
+            double dd;
+            const double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
+            const bool acc = in && t > cur.c;
+            if (acc) Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, zw);
             const uint64_t rej = __ballot(in && !acc);
             if (STATS) {
                 const uint64_t am = __ballot(acc);

@@ -120,6 +120,9 @@ def _dev(t: torch.Tensor, name: str, dtype=None):
     return t
 
 
+DEFAULT_ITEM_POINTS = 256  # the library's default work-item size
+
+
 class Context:
     """hts_ctx on one device."""
 
@@ -128,6 +131,7 @@ class Context:
         _ck(lib().hts_create(int(device), C.byref(h)))
         self.h = h
         self.device = device
+        self.item_points = DEFAULT_ITEM_POINTS
 
     def close(self):
         if getattr(self, "h", None):
