@@ -178,3 +178,36 @@ def test_cosne_terms_match_oracle(ctx, dtype, theta):
     gk, _, _ = oracle.gradient_bh(Yo, rp, col, v.astype(np.float64), oracle.Tree(Yo), theta, 1.0)
     go = oracle.cosne_gradient(Yo, xn2, 0.7, 2.0, gk)
     assert rel(gd.cpu().numpy(), go) < (1e-3 if dtype == np.float32 else 1e-10)
+
+
+@pytest.mark.parametrize("theta", [1.0, 1.5, 3.0])
+def test_bh_large_theta_root_accepted(ctx, theta):
+    # theta >= 1: a query may accept the root cell itself; its term must be
+    # counted once although every phase-A wave of the block tests the root
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, "mid", np.float64)
+    g, z, st = _run_bh(ctx, Y, rp, col, val, 1.0, theta, stats=True)
+    t = oracle.Tree(Y)
+    go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, theta, 1.0)
+    assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    assert rel(g, go) < 1e-10
+    assert z == pytest.approx(zo, rel=1e-10)
+
+
+@pytest.mark.parametrize("item_points", [1, 16, 64, 2048, 1 << 20])
+def test_bh_work_item_sizes(ctx, item_points):
+    # tiny items (phase A walks deep and fills its item buffers), huge items
+    # (the whole tree is one item per query block): the result and the
+    # counters do not depend on the split between the two phases
+    X, _, rp, col, val = affinities(3000)
+    Y = embedding(3000, "late", np.float64)
+    ctx.set_item_points(item_points)
+    try:
+        g, z, st = _run_bh(ctx, Y, rp, col, val, 12.0, 0.5, stats=True)
+    finally:
+        ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
+    t = oracle.Tree(Y)
+    go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 12.0)
+    assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    assert rel(g, go) < 1e-10
+    assert z == pytest.approx(zo, rel=1e-10)

@@ -223,3 +223,20 @@ def test_driver_iterations_match_oracle(ctx, lam):
             g, _, _ = oracle.hsne_gradient_bh(Y, rp, col, val, t, 0.5, lam, ex)
         Y, U, G = oracle.step(Y, U, G, g, eta, mu)
     assert rel(Yg, Y) < 1e-9
+
+
+@pytest.mark.parametrize("item_points", [16, 1 << 20])
+@pytest.mark.parametrize("theta", [0.5, 1.5])
+def test_hsne_work_item_sizes_and_large_theta(ctx, item_points, theta):
+    X, _, rp, col, val = affinities(1500)
+    Y = embedding(1500, "late", np.float64)
+    ctx.set_item_points(item_points)
+    try:
+        g, z, st = _run(ctx, Y, rp, col, val, 12.0, 0.6, theta, stats=True)
+    finally:
+        ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
+    go, ze, zh, ce, ch = _oracle(Y, rp, col, val, 12.0, 0.6, theta)
+    assert st[:3] == [ce["tests"], ce["accepts"], ce["pairs"]]
+    assert st[10:13] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    assert rel(g, go) < 1e-10
+    assert z[0] == pytest.approx(ze, rel=1e-10)
