@@ -32,13 +32,15 @@ struct PairTerm {
     T vx, vy; // (q - o) + |q - o|^2 ia_q q
 };
 
-// distance argument in double from coordinates in T
+// distance argument in double from coordinates in T.  dd (2 qia) rounds to
+// the same value as (2 dd) qia (the factor 2 is exact), and 2 qia is the
+// same for every node a query meets, so it is formed once per walk.
 template <typename T>
 __device__ __forceinline__ double dist_arg(T qx, T qy, double qia, T ox, T oy, double oib, double &dd) {
     double dx = (double)qx - (double)ox;
     double dy = (double)qy - (double)oy;
     dd = dx * dx + dy * dy;
-    return 2.0 * dd * qia * oib;
+    return dd * (2.0 * qia) * oib;
 }
 
 // double precision: library functions throughout
