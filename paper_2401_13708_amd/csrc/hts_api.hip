@@ -441,10 +441,9 @@ static hts_status bh_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, cons
     HTS_OKR(ensure(c->pts, (size_t)n * sizeof(PointRec<T>)));
     HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
     PointRec<T> *pts = (PointRec<T> *)c->pts.p;
-    HTS_OKR(tree_thresholds(c, st, t, sizeof(T) == 8 ? HTS_F64 : HTS_F32, theta));
-    HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
-    return launch_bh_repulsion<T, 0>(c, st, t, n, pts, rp, col, val, (T *)c->fattr.p, ex, ex_job,
-                                     false, 1.0, grad, z_dev, stats);
+    return launch_bh_repulsion<T, 0>(c, st, t, n, BhPrep<T>{Y, theta, true, true}, pts, rp, col,
+                                     val, (T *)c->fattr.p, ex, ex_job, false, 1.0, grad, z_dev,
+                                     stats);
 }
 
 static hts_status bh_tree_args(const char *fn, hts_ctx c, hts_tree t, int64_t n, int32_t dtype,
@@ -528,14 +527,14 @@ static hts_status hsne_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, co
     HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
     PointRec<T> *pts = (PointRec<T> *)c->pts.p;
     T *fattr = (T *)c->fattr.p;
-    HTS_OKR(tree_thresholds(c, st, t, sizeof(T) == 8 ? HTS_F64 : HTS_F32, theta));
     HTS_OKR(tree_euclid<T>(c, st, t, theta));
-    HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
-    // Euclidean part into grad, then grad + lambda (hyperbolic part)
-    HTS_OKR((launch_bh_repulsion<T, 1>(c, st, t, n, pts, rp, col, val, fattr, ex, nullptr, false,
-                                       1.0, grad, z_dev, stats)));
-    return launch_bh_repulsion<T, 0>(c, st, t, n, pts, rp, col, val, fattr, ex, nullptr, true,
-                                     lambda, grad, z_dev + 1, stats ? stats + 10 : nullptr);
+    // Euclidean part into grad (its launch writes the point records), then
+    // grad + lambda (hyperbolic part) (its launch sets the node thresholds)
+    HTS_OKR((launch_bh_repulsion<T, 1>(c, st, t, n, BhPrep<T>{Y, theta, true, false}, pts, rp, col,
+                                       val, fattr, ex, nullptr, false, 1.0, grad, z_dev, stats)));
+    return launch_bh_repulsion<T, 0>(c, st, t, n, BhPrep<T>{Y, theta, false, true}, pts, rp, col,
+                                     val, fattr, ex, nullptr, true, lambda, grad, z_dev + 1,
+                                     stats ? stats + 10 : nullptr);
 }
 
 extern "C" {

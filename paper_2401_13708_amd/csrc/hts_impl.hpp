@@ -186,8 +186,6 @@ inline Jobs jobs_of(hts_tree t) {
     return Jobs{t->job_off, t->job_qb, t->qb_job, t->pjob, t->J};
 }
 
-hts_status tree_thresholds(hts_ctx ctx, hipStream_t st, hts_tree t, int dtype, double theta);
-
 // Euclidean node records (centres of mass, thresholds for theta) of the last
 // build, for the h-SNE term
 template <typename T>
@@ -203,6 +201,17 @@ template <typename T>
 hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, const int64_t *rp,
                           const int32_t *col, const T *val, int64_t n, T *fattr);
 
+// What the launch that starts a traversal also does: the point records of Y
+// into pts (points) and the criterion thresholds of the tree's hyperbolic
+// nodes for theta (thresholds).
+template <typename T>
+struct BhPrep {
+    const T *Y;
+    double theta;
+    bool points;
+    bool thresholds;
+};
+
 // Barnes-Hut repulsion over the tree and the combine g = 4 (a F_attr - F_rep / Z)
 // ex_job: per-job exaggeration (device, [J]) or NULL for ex; z_dev receives
 // Z of every job ([J]); with accumulate, grad + scale g is stored.
@@ -211,10 +220,10 @@ hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, c
 // (the first launch also computes the attractive term into fattr)
 template <typename T, int MET>
 hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n,
-                               const PointRec<T> *pts, const int64_t *rp, const int32_t *col,
-                               const T *val, T *fattr, double ex, const double *ex_job,
-                               bool accumulate, double scale, T *grad, double *z_dev,
-                               uint64_t *stats);
+                               BhPrep<T> prep, PointRec<T> *pts, const int64_t *rp,
+                               const int32_t *col, const T *val, T *fattr, double ex,
+                               const double *ex_job, bool accumulate, double scale, T *grad,
+                               double *z_dev, uint64_t *stats);
 
 template <typename T>
 hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,

@@ -172,6 +172,35 @@ template <> struct Geo<1> {
     }
 };
 
+// ---------------------------------------------------------------- set-up
+// Point record of Y[i] (coordinates and 1 / (1 - |y|^2) in double); a point
+// outside the open disk or not finite sets the error word.
+template <typename T>
+__device__ __forceinline__ void prep_point(const T *__restrict__ Y, int64_t i,
+                                           PointRec<T> *__restrict__ pts,
+                                           uint32_t *__restrict__ err) {
+    const T x = Y[2 * i], y = Y[2 * i + 1];
+    const double a = 1.0 - ((double)x * (double)x + (double)y * (double)y);
+    PointRec<T> p;
+    p.x = x;
+    p.y = y;
+    p.ia = 1.0 / a;
+    if constexpr (sizeof(T) == 8) p.pad = 0.0;
+    if (!(a > 0.0)) atomicOr(err, (a == a) ? HTS_ERR_OUTSIDE_DISK : HTS_ERR_NONFINITE_Y);
+    pts[i] = p;
+}
+
+// Criterion threshold of an internal node: r_cell / d < theta  <=>
+// t > cosh(r_cell / theta) - 1 = 2 sinh^2(r_cell / (2 theta)) (the sinh form
+// keeps small thresholds accurate); theta = 0 never accepts.
+__device__ __forceinline__ double node_threshold(double r_cell, double theta) {
+    if (theta > 0.0) {
+        const double sh = sinh(r_cell / (2.0 * theta));
+        return 2.0 * sh * sh;
+    }
+    return __builtin_inf();
+}
+
 // ---------------------------------------------------------------- wave ops
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -290,10 +290,29 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     }
 }
 
-// clears the dense-list counter (a kernel, not a memset, so the sequence can
-// be captured in a graph)
-__global__ void k_zero_u32(unsigned *p) {
-    if (threadIdx.x == 0) *p = 0u;
+// Before a traversal: clears the item-list counter (a kernel, not a memset,
+// so the sequence can be captured in a graph), and as asked writes the point
+// records of Y and the criterion thresholds of the internal nodes.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bh_prepare(const T *__restrict__ Y, int64_t n,
+                                                       PointRec<T> *__restrict__ pts, bool points,
+                                                       NodeRec<T> *__restrict__ nodes,
+                                                       const double *__restrict__ r_cell,
+                                                       const int32_t *__restrict__ d_m,
+                                                       double theta, bool thresholds,
+                                                       unsigned *__restrict__ dense_count,
+                                                       uint32_t *__restrict__ err) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) *dense_count = 0u;
+    if (points && i < n) prep_point<T>(Y, i, pts, err);
+    if (thresholds) {
+        const int64_t M = *d_m;
+        const int64_t G = (int64_t)gridDim.x * kBlock;
+        for (int64_t k = i; k < M; k += G) {
+            const uint32_t next = nodes[k].next_depth & kNextMask;
+            if ((int64_t)next != k + 1) nodes[k].c = node_threshold(r_cell[k], theta);
+        }
+    }
 }
 
 // one item record in scalar registers
@@ -433,44 +452,51 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
     }
 }
 
-// Combine, stage 2: Z of every job = the sum of its block totals in block
-// order (one workgroup per job, a fixed reduction tree) ...
-__global__ __launch_bounds__(kBlock) void k_bh_zjob(const double *__restrict__ zq, Jobs jb,
-                                                    double *__restrict__ zjob,
-                                                    double *__restrict__ z_dev) {
-    __shared__ double sh[kBlock];
-    const int j = blockIdx.x;
-    const int64_t a0 = jb.job_qb[j], a1 = jb.job_qb[j + 1];
-    double s = 0.0;
-    for (int64_t a = a0 + threadIdx.x; a < a1; a += kBlock) s += zq[a];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        zjob[j] = sh[0];
-        z_dev[j] = sh[0];
-    }
-}
-
-// ... then g_i = 4 (a F_attr,i - F_rep,i / Z) scattered to input order; with
-// `accumulate`, grad_i + scale g_i is stored instead (the second term of a sum
-// of gradients)
+// Combine, stage 2: g_i = 4 (a F_attr,i - F_rep,i / Z) scattered to input
+// order; with `accumulate`, grad_i + scale g_i is stored instead (the second
+// term of a sum of gradients).  Z of a job is the sum of its query blocks'
+// totals, formed by every workgroup that holds points of the job the same way
+// (one wave: four lane-strided partial sums per lane, then a fixed butterfly), so
+// all of them use the same value; the workgroup holding the job's first point
+// writes it to z_dev.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bh_finalize(
-    const T *__restrict__ fattr, const T *__restrict__ frep, const double *__restrict__ zjob,
-    const int32_t *__restrict__ pjob, const uint32_t *__restrict__ perm, int64_t n, double ex,
+    const T *__restrict__ fattr, const T *__restrict__ frep, const double *__restrict__ zq,
+    Jobs jb, const uint32_t *__restrict__ perm, int64_t n, double ex,
     const double *__restrict__ ex_job, bool accumulate, double scale, T *__restrict__ grad,
-    uint32_t *__restrict__ err) {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double *__restrict__ z_dev, uint32_t *__restrict__ err) {
+    __shared__ double s_z[kBlock];  // a job holds at least one point of the workgroup
+    const int64_t b0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t bl = (b0 + kBlock < n ? b0 + kBlock : n) - 1;
+    const int j0 = jb.pjob[b0], j1 = jb.pjob[bl];
+    const int wave = (int)(threadIdx.x / kWave), lane = (int)(threadIdx.x & (kWave - 1));
+    for (int j = j0 + wave; j <= j1; j += kBlock / kWave) {
+        const int64_t a0 = jb.job_qb[j], a1 = jb.job_qb[j + 1];
+        // four partial sums per lane keep four loads in flight
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+        int64_t a = a0 + lane;
+        for (; a + 3 * kWave < a1; a += 4 * kWave) {
+            z0 += zq[a];
+            z1 += zq[a + kWave];
+            z2 += zq[a + 2 * kWave];
+            z3 += zq[a + 3 * kWave];
+        }
+        for (; a < a1; a += kWave) z0 += zq[a];
+        const double zs = wave_sum((z0 + z1) + (z2 + z3));
+        if (lane == 0) {
+            s_z[j - j0] = zs;
+            const int64_t f = jb.off[j];
+            if (f >= b0 && f <= bl) z_dev[j] = zs;
+        }
+    }
+    __syncthreads();
+    const int64_t q = b0 + threadIdx.x;
     if (q >= n) return;
     // sorted positions of a job cover the same range as its input points
-    const int job = pjob[q];
+    const int job = jb.pjob[q];
     const double a = ex_job ? ex_job[job] : ex;
     const uint32_t i = perm[q];
-    const double inv = 1.0 / zjob[job];
+    const double inv = 1.0 / s_z[job - j0];
     double gx = 4.0 * (a * (double)fattr[2 * (int64_t)i] - (double)frep[2 * q] * inv);
     double gy = 4.0 * (a * (double)fattr[2 * (int64_t)i + 1] - (double)frep[2 * q + 1] * inv);
     if (accumulate) {
@@ -485,10 +511,10 @@ __global__ __launch_bounds__(kBlock) void k_bh_finalize(
 
 template <typename T, int MET>
 hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n,
-                               const PointRec<T> *pts, const int64_t *rp, const int32_t *col,
-                               const T *val, T *fattr, double ex, const double *ex_job,
-                               bool accumulate, double scale, T *grad, double *z_dev,
-                               uint64_t *stats) {
+                               BhPrep<T> prep, PointRec<T> *pts, const int64_t *rp,
+                               const int32_t *col, const T *val, T *fattr, double ex,
+                               const double *ex_job, bool accumulate, double scale, T *grad,
+                               double *z_dev, uint64_t *stats) {
     const int64_t nqb = t->nqb;
     const Jobs jb = jobs_of(t);
     const int64_t nw = nqb * kTopSlots;  // phase-A waves
@@ -501,11 +527,10 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const size_t b_frep = (size_t)n * 2 * sizeof(T), b_zq = (size_t)nqb * 8;
     const size_t b_st = stats ? (size_t)(slots + nw) * kStats * 4 : 0;
     const size_t b_cnt = 256, b_dense = (size_t)slots * sizeof(ItemRec);
-    const size_t b_zjob = (size_t)t->J * 8;
-    constexpr int R = 12;
+    constexpr int R = 11;
     size_t off[R], tot = 0;
     const size_t sizes[R] = {b_base, b_nit, b_part0, b_ztop, b_part, b_zitem,
-                             b_frep, b_zq, b_st, b_cnt, b_dense, b_zjob};
+                             b_frep, b_zq, b_st, b_cnt, b_dense};
     for (int a = 0; a < R; ++a) {
         off[a] = tot;
         tot += (sizes[a] + 255) & ~(size_t)255;
@@ -524,14 +549,17 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     uint32_t *st_top = stats ? st_items + (size_t)slots * kStats : nullptr;
     unsigned *dense_count = (unsigned *)(base + off[9]);
     ItemRec *dense = (ItemRec *)(base + off[10]);
-    double *zjob = (double *)(base + off[11]);
 
     const NodeRec<T> *nodes = (const NodeRec<T> *)(MET == 0 ? t->nodes : t->enodes);
     const PointRec<T> *spts = (const PointRec<T> *)t->spts;
     const dim3 gq(cdiv(nqb, kBlock / kWave));
     int64_t gi = cdiv(slots, kBlock / kWave);
     if (gi > 16384) gi = 16384;  // several waves per SIMD slot: the hardware balances the load
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kWave), 0, st, dense_count);
+    // one thread per point, and the node thresholds strided over the same grid
+    const int64_t gp = cdiv(n, kBlock) > 64 ? cdiv(n, kBlock) : 64;
+    hipLaunchKernelGGL(k_bh_prepare<T>, dim3(gp), dim3(kBlock), 0, st, prep.Y, n, pts, prep.points,
+                       (NodeRec<T> *)t->nodes, t->r_cell, t->d_m, prep.theta, prep.thresholds,
+                       dense_count, ctx->d_err);
     {
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
         const int64_t top_blocks = cdiv(nw, kBlock / kWave);
@@ -566,31 +594,30 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
         hipLaunchKernelGGL((k_bh_gather<T, false>), gq, dim3(kBlock), 0, st, part0, ztop, part,
                            zitem, item_base, nitems, jb, nqb, n, frep, zq, nullptr, nullptr,
                            nullptr);
-    hipLaunchKernelGGL(k_bh_zjob, dim3(t->J), dim3(kBlock), 0, st, zq, jb, zjob, z_dev);
     hipLaunchKernelGGL(k_bh_finalize<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,
-                       zjob, t->pjob, t->perm, n, ex, ex_job, accumulate, scale, grad,
+                       zq, jb, t->perm, n, ex, ex_job, accumulate, scale, grad, z_dev,
                        ctx->d_err);
     HTS_HIP(hipGetLastError());
     return HTS_OK;
 }
 
 template hts_status launch_bh_repulsion<float, 0>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                                   const PointRec<float> *, const int64_t *,
+                                                   BhPrep<float>, PointRec<float> *, const int64_t *,
                                                    const int32_t *, const float *, float *, double,
                                                    const double *, bool, double, float *, double *,
                                                    uint64_t *);
 template hts_status launch_bh_repulsion<float, 1>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                                   const PointRec<float> *, const int64_t *,
+                                                   BhPrep<float>, PointRec<float> *, const int64_t *,
                                                    const int32_t *, const float *, float *, double,
                                                    const double *, bool, double, float *, double *,
                                                    uint64_t *);
 template hts_status launch_bh_repulsion<double, 0>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                                   const PointRec<double> *, const int64_t *,
+                                                   BhPrep<double>, PointRec<double> *, const int64_t *,
                                                    const int32_t *, const double *, double *, double,
                                                    const double *, bool, double, double *, double *,
                                                    uint64_t *);
 template hts_status launch_bh_repulsion<double, 1>(hts_ctx, hipStream_t, hts_tree, int64_t,
-                                                   const PointRec<double> *, const int64_t *,
+                                                   BhPrep<double>, PointRec<double> *, const int64_t *,
                                                    const int32_t *, const double *, double *, double,
                                                    const double *, bool, double, double *, double *,
                                                    uint64_t *);

@@ -12,17 +12,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prep_points(const T *__restrict__ Y, int64_t n,
                                                         PointRec<T> *__restrict__ pts,
                                                         uint32_t *__restrict__ err) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    T x = Y[2 * i], y = Y[2 * i + 1];
-    double a = 1.0 - ((double)x * (double)x + (double)y * (double)y);
-    PointRec<T> p;
-    p.x = x;
-    p.y = y;
-    p.ia = 1.0 / a;
-    if constexpr (sizeof(T) == 8) p.pad = 0.0;
-    if (!(a > 0.0)) atomicOr(err, (a == a) ? HTS_ERR_OUTSIDE_DISK : HTS_ERR_NONFINITE_Y);
-    pts[i] = p;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) prep_point<T>(Y, i, pts, err);
 }
 
 template <typename T>

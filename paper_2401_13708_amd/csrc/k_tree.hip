@@ -93,18 +93,16 @@ __global__ __launch_bounds__(kBlock) void k_polar(const T *__restrict__ Y, int64
     }
 }
 
-// one wave per job that spans several blocks: its range from the partials
-__global__ __launch_bounds__(kBlock) void k_root(const int64_t *__restrict__ job_off, int J,
-                                                 const double *__restrict__ mm,
-                                                 double *__restrict__ root) {
-    const int j = (int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
-    if (j >= J) return;
-    const int lane = (int)(threadIdx.x & (kWave - 1));
+// The (min, max) of r of a job that spans several blocks, from the partials
+// k_polar leaves: the job is the last one of its first block and the first
+// one of every later block (one wave; min and max are exact in any order).
+__device__ __forceinline__ void job_range(const int64_t *__restrict__ job_off, int j,
+                                          const double *__restrict__ mm, int lane, double &lo,
+                                          double &hi) {
     const int64_t b0 = job_off[j] / kBlock, b1 = (job_off[j + 1] - 1) / kBlock;
-    if (b0 == b1) return;  // reduced in k_polar
     double vmin = __builtin_inf(), vmax = -__builtin_inf();
     for (int64_t b = b0 + lane; b <= b1; b += kWave) {
-        const int h = b == b0 ? 2 : 0;  // the job is the last one of block b0, the first of the rest
+        const int h = b == b0 ? 2 : 0;
         vmin = fmin(vmin, mm[4 * b + h]);
         vmax = fmax(vmax, mm[4 * b + h + 1]);
     }
@@ -113,10 +111,8 @@ __global__ __launch_bounds__(kBlock) void k_root(const int64_t *__restrict__ job
         vmin = fmin(vmin, __shfl_xor(vmin, o, 64));
         vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
     }
-    if (lane == 0) {
-        root[2 * j] = vmin;
-        root[2 * j + 1] = vmax;
-    }
+    lo = vmin;
+    hi = vmax;
 }
 
 // Radial split point of a cell with embedding radii [lo, hi]: rule 0 halves
@@ -136,18 +132,55 @@ __device__ __forceinline__ double radial_mid(double lo, double hi, int rule) {
 
 // ---------------------------------------------------------------- 2. keys
 // job index above max_depth levels of the split rule, two bits per level
-// (radial bit: r >= (lo + hi) / 2 of eq. (10); angular bit: phi >= (lo + hi) / 2)
+// (radial bit: r at or above the radial split; angular bit:
+// phi >= (lo + hi) / 2).  A job inside one block has its root annulus from
+// k_polar; the block's first and last jobs may span other blocks, and their
+// annuli are reduced here from k_polar's partials (the block holding a job's
+// first point stores it for the later kernels).
 __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
                                                  const double *__restrict__ phi, int64_t n,
                                                  const int32_t *__restrict__ pjob,
-                                                 const double *__restrict__ root, int L,
-                                                 int split, uint64_t *__restrict__ keys,
+                                                 const int64_t *__restrict__ job_off,
+                                                 const double *__restrict__ mm,
+                                                 double *__restrict__ root, int L, int split,
+                                                 uint64_t *__restrict__ keys,
                                                  uint32_t *__restrict__ idx) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    __shared__ double s_range[2][2];
+    const int64_t b0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t bl = (b0 + kBlock < n ? b0 + kBlock : n) - 1;
+    const int jf = pjob[b0], jl = pjob[bl];
+    const int wave = (int)(threadIdx.x / kWave), lane = (int)(threadIdx.x & (kWave - 1));
+    if (wave < 2) {
+        const int j = wave == 0 ? jf : jl;
+        const bool spans = job_off[j] / kBlock != (job_off[j + 1] - 1) / kBlock;
+        if (spans && (wave == 0 || jl != jf)) {
+            double lo, hi;
+            job_range(job_off, j, mm, lane, lo, hi);
+            if (lane == 0) {
+                s_range[wave][0] = lo;
+                s_range[wave][1] = hi;
+                if (job_off[j] >= b0 && job_off[j] <= bl) {
+                    root[2 * j] = lo;
+                    root[2 * j + 1] = hi;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t i = b0 + threadIdx.x;
     if (i >= n) return;
     const int job = pjob[i];
+    double lo, hi;
+    if (job_off[job] / kBlock == (job_off[job + 1] - 1) / kBlock) {
+        lo = root[2 * job];
+        hi = root[2 * job + 1];
+    } else {
+        const int w = job == jf ? 0 : 1;
+        lo = s_range[w][0];
+        hi = s_range[w][1];
+    }
     double rv = r[i], pv = phi[i];
-    double lo = root[2 * job], hi = root[2 * job + 1], plo = 0.0, phh = kTwoPi;
+    double plo = 0.0, phh = kTwoPi;
     uint64_t key = (uint64_t)job;
     for (int l = 0; l < L; ++l) {
         double mr = radial_mid(lo, hi, split);
@@ -300,10 +333,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt
     }
 }
 
+// Applies the block offsets: node_start[i] (in place of the node counts) and
+// the exclusive midpoint-summand sums; then every point records itself as the
+// first point of the nodes it starts (node_first), which are stored
+// consecutively from node_start[i].
 __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t *__restrict__ cnt,
                                                        DD3 *__restrict__ q, int64_t n,
                                                        const int32_t *__restrict__ cnt_part,
-                                                       const DD3 *__restrict__ q_part) {
+                                                       const DD3 *__restrict__ q_part,
+                                                       int32_t *__restrict__ node_first,
+                                                       int64_t cap, uint32_t *__restrict__ err) {
     __shared__ int scnt[kBlock];
     __shared__ DD3 sq[kBlock];
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -326,10 +365,20 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t *__restrict__ cnt
         __syncthreads();
     }
     if (i < n) {
-        int ex_c = threadIdx.x > 0 ? scnt[threadIdx.x - 1] : 0;
-        DD3 ex_v = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd_zero();
-        cnt[i] = cnt_part[blockIdx.x] + ex_c;
+        const int ex_c = threadIdx.x > 0 ? scnt[threadIdx.x - 1] : 0;
+        const DD3 ex_v = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd_zero();
+        const int c = scnt[threadIdx.x] - ex_c;  // nodes starting at i
+        const int32_t base = cnt_part[blockIdx.x] + ex_c;
+        cnt[i] = base;
         q[i] = dd_add(q_part[blockIdx.x], ex_v);
+        for (int a = 0; a < c; ++a) {
+            const int64_t k = (int64_t)base + a;
+            if (k >= cap) {  // cannot happen for a consistent scan; never write past the storage
+                atomicOr(err, HTS_ERR_TREE_OVERFLOW);
+                break;
+            }
+            node_first[k] = (int32_t)i;
+        }
     }
 }
 
@@ -383,27 +432,7 @@ __device__ __forceinline__ int64_t cell_end(const uint64_t *__restrict__ keys, i
     return lo;
 }
 
-// 6a. every node records the sorted position of its first point (a point
-// starts the nodes of depths s..D, stored consecutively from node_start[i])
-__global__ __launch_bounds__(kBlock) void k_emit_first(const uint64_t *__restrict__ keys, int64_t n,
-                                                       int L, const int32_t *__restrict__ node_start,
-                                                       int32_t *__restrict__ node_first, int64_t cap,
-                                                       uint32_t *__restrict__ err) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const NodeSpan sp = node_span(keys, i, n, L);
-    const int32_t base = node_start[i];
-    for (int l = sp.s; l <= sp.D; ++l) {
-        const int32_t k = base + (l - sp.s);
-        if (k >= cap) {  // cannot happen for a consistent scan; never write past the storage
-            atomicOr(err, HTS_ERR_TREE_OVERFLOW);
-            return;
-        }
-        node_first[k] = (int32_t)i;
-    }
-}
-
-// 6b. one thread per node: count, subtree end, leaf point or Einstein
+// 6. one thread per node: count, subtree end, leaf point or Einstein
 // midpoint, and cell diameter (threads of a wave do equal work, whatever the
 // length of their points' chains of nodes)
 template <typename T>
@@ -464,27 +493,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
     r_cell[k] = log1p(t + sqrt(t * (t + 2.0)));
 }
 
-// criterion threshold per internal node: r_cell / d < theta  <=>  t > cosh(r_cell / theta) - 1
-// = 2 sinh^2(r_cell / (2 theta)) (the sinh form keeps small thresholds accurate)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_threshold(NodeRec<T> *__restrict__ nodes,
-                                                      const double *__restrict__ r_cell,
-                                                      const int32_t *__restrict__ d_m,
-                                                      double theta) {
-    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= *d_m) return;
-    uint32_t next = nodes[k].next_depth & kNextMask;
-    if ((int64_t)next == k + 1) return;  // leaf
-    double c;
-    if (theta > 0.0) {
-        double sh = sinh(r_cell[k] / (2.0 * theta));
-        c = 2.0 * sh * sh;
-    } else {
-        c = __builtin_inf();
-    }
-    nodes[k].c = c;
-}
-
 __global__ void k_single_job(int64_t *__restrict__ job_off, int32_t *__restrict__ job_qb,
                              int64_t n) {
     if (threadIdx.x == 0) {
@@ -513,11 +521,8 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     hipLaunchKernelGGL(k_polar<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->pjob, t->job_off, t->r,
                        t->phi, t->mm, t->root);
     HTS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_root, dim3(cdiv(t->J, kBlock / kWave)), dim3(kBlock), 0, st, t->job_off,
-                       t->J, t->mm, t->root);
-    HTS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kBlock), 0, st, t->r, t->phi, n, t->pjob, t->root, L,
-                       t->split_rule, t->keys_in, t->idx_in);
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kBlock), 0, st, t->r, t->phi, n, t->pjob, t->job_off,
+                       t->mm, t->root, L, t->split_rule, t->keys_in, t->idx_in);
     HTS_HIP(hipGetLastError());
     HTS_OKR(radix_sort_pairs(st, t->keys_in, t->idx_in, t->keys, t->perm, n, 2 * L + t->job_bits,
                              t->sort_tmp));
@@ -528,10 +533,7 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
                        t->node_start, t->psum, n, t->d_m, t->cap_nodes, ctx->d_err);
     HTS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, st, t->node_start, t->psum, n,
-                       t->ncnt_part, t->q_part);
-    HTS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_emit_first, dim3(nb), dim3(kBlock), 0, st, t->keys, n, L, t->node_start,
-                       t->node_first, t->cap_nodes, ctx->d_err);
+                       t->ncnt_part, t->q_part, t->node_first, t->cap_nodes, ctx->d_err);
     HTS_HIP(hipGetLastError());
     // over the node capacity for n points; the kernel reads the live count
     int64_t nbm = cdiv(n * (int64_t)(L + 1) + 1, kBlock);
@@ -549,21 +551,6 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
 hts_status tree_sort_bytes(int64_t n_max, int L, size_t *bytes) {
     (void)L;
     *bytes = radix_sort_temp_bytes(n_max);
-    return HTS_OK;
-}
-
-hts_status tree_thresholds(hts_ctx ctx, hipStream_t st, hts_tree t, int dtype, double theta) {
-    int64_t nbm = cdiv(t->cap_nodes, kBlock);
-    // launch over the capacity; the kernel reads the live node count itself
-    int64_t bound = cdiv(t->n * (t->max_depth + 1) + 1, kBlock);
-    if (bound < nbm) nbm = bound;
-    if (dtype == HTS_F64)
-        hipLaunchKernelGGL(k_threshold<double>, dim3(nbm), dim3(kBlock), 0, st,
-                           (NodeRec<double> *)t->nodes, t->r_cell, t->d_m, theta);
-    else
-        hipLaunchKernelGGL(k_threshold<float>, dim3(nbm), dim3(kBlock), 0, st,
-                           (NodeRec<float> *)t->nodes, t->r_cell, t->d_m, theta);
-    HTS_HIP(hipGetLastError());
     return HTS_OK;
 }
 
