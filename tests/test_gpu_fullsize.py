@@ -9,6 +9,9 @@ library calls and launch configuration the benchmark times.
   exact gradient (sampled rows, with the oracle's all-pairs Z) and the step.
 * N = 200000, D = 50 (the hierarchical workload): kNN rows sampled, and the
   Barnes-Hut gradient at theta in {0.3, 0.5, 0.8} against the oracle.
+* N = 3.1 million (near the largest tree the 26-bit node indices allow at
+  depth 20): the whole tree bit-exact; N = 1 million: the whole Barnes-Hut
+  gradient against the oracle.
 
 The oracle finishes each of these in seconds (Barnes-Hut and the tree are
 O(n log n); kNN and exact rows are computed one row at a time)."""
@@ -141,6 +144,40 @@ def test_bh_headline_size(ctx, stage):
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.8])
 def test_bh_hierarchical_size(ctx, theta):
     _bh_against_oracle(ctx, N_HIER, "mid", theta, 1.0, 12)
+
+
+# The node storage of a tree holds n_max (max_depth + 1) + 1 records, indexed
+# with 26 bits: at depth 20 the largest n_max is 3,195,660.
+N_NEAR_MAX = 3_100_000
+
+
+@pytest.mark.timeout(300)  # the oracle's insertion build of 3.1 million points
+def test_tree_near_max_size(ctx):
+    # the whole tree at the largest size the node indices allow, node for node
+    Y = embedding(N_NEAR_MAX, "mid", np.float32)
+    t = hts.Tree(ctx, N_NEAR_MAX, 20)
+    hts.build_polar_tree(ctx, torch.from_numpy(Y).cuda(), t)
+    g = hts.tree_export(ctx, t, N_NEAR_MAX)
+    t.close()
+    assert ctx.check() == 0
+    o = oracle.Tree(Y.astype(np.float64)).export()
+    assert g["count"].size == o["count"].size
+    for key in ("count", "depth", "first", "next"):
+        assert np.array_equal(g[key], o[key]), key
+    assert np.array_equal(g["perm"], o["perm"].astype(np.int32))
+
+
+@pytest.mark.timeout(300)  # the oracle's Barnes-Hut over one million queries
+def test_bh_million_points(ctx):
+    # the whole Barnes-Hut gradient at one million points (single precision)
+    n = 1_000_000
+    Y = embedding(n, "late", np.float32)
+    rp, col, v32 = synth.random_csr(n, 20, seed=14, dtype=np.float32)
+    g, z = _bh(ctx, Y, rp, col, v32, 0.5, 12.0)
+    Yo = Y.astype(np.float64)
+    go, zo, _ = oracle.gradient_bh(Yo, rp, col, v32.astype(np.float64), oracle.Tree(Yo), 0.5, 12.0)
+    assert rel(g, go) < 1e-3
+    assert z == pytest.approx(zo, rel=1e-5)
 
 
 def test_exact_headline_size_sampled_rows(ctx):

@@ -55,6 +55,7 @@ def test_library_is_gfx950_code():
                                       C.byref(C.c_int64())), "not in [1, n)"),
     (lambda L: L.hts_tree_create(None, 1, 20, C.byref(C.c_void_p())), "n_max < 2"),
     (lambda L: L.hts_tree_create(None, 100, 40, C.byref(C.c_void_p())), "max_depth"),
+    (lambda L: L.hts_tree_create(None, 3_195_661, 20, C.byref(C.c_void_p())), "2^26"),
     (lambda L: L.hts_build_polar_tree(None, None, None, 10, 0, None), "NULL handle"),
 ])
 def test_host_validation(call, msg):
