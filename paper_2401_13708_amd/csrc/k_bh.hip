@@ -16,17 +16,23 @@
 //
 // One wave walking the whole tree for its block is a long serial chain, so the
 // walk is split in two phases:
-//  A. one wave per query block walks the nodes that hold more than S points;
-//     when some lanes reject a smaller cell, the cell and their mask become a
-//     work item instead of being descended;
+//  A. four waves per query block, one per subtree below the root, walk the
+//     nodes that hold more than S points; when some lanes reject a smaller
+//     cell, the cell and their mask become a work item instead of being
+//     descended;
 //  B. waves walk the work items, each a short independent chain; an item
 //     record is self-contained (subtree, lane mask, query block).  The grid
 //     holds several times the waves that fit on the chip, so the hardware
 //     hands the next waves (and their items) to whichever SIMD frees up.
 // Every item writes its own partial force per lane and partial Z; the items
-// of a query block occupy one contiguous run of the item list, and the
-// combine adds them in emission order, so the result does not depend on
-// scheduling.
+// of a phase-A wave occupy one contiguous run of the item list, and the
+// combine adds, per query block, its waves' partials and runs in a fixed
+// order, so the result does not depend on scheduling.
+//
+// The walk is written once over a metric (Geo<MET>): the Poincare disk for
+// the hyperbolic gradient, and the Euclidean Student-t kernel of the disk
+// coordinates for the first part of the h-SNE gradient (Sec. 3), which walks
+// the same tree with Euclidean node records.
 #include "hts_impl.hpp"
 #include "hts_math.hpp"
 
@@ -61,7 +67,8 @@ struct Counters {
 // Depth-first walk of the pre-order range [k, kend), which starts at a node
 // of depth d0 and holds its subtree, for the lanes in mask0.  With EMIT, an
 // internal node of at most S points that some lanes reject is appended to the
-// block's item list (while there is room) instead of being descended.
+// wave's item list (while there is room) instead of being descended.  The
+// walk's Z terms are summed in T and added to z once at the end.
 // Node records are read with scalar loads (the node index is uniform);
 // both possible successors are fetched while a node is evaluated.
 template <typename T, int MET, bool STATS, bool EMIT>
