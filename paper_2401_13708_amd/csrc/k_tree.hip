@@ -2,8 +2,10 @@
 //
 // The tree is built from sorted (r, phi) keys instead of by insertion:
 //  1. polar position of every point (double, from the single-precision
-//     coordinates) and per-block min/max of r;
-//  2. key of every point: max_depth levels of the split rule, two bits per
+//     coordinates) and per-block min/max of r per job;
+//  2. root annulus of every job (a job spanning blocks is reduced from the
+//     block partials), then the key of every point: max_depth levels of the
+//     split rule, two bits per
 //     level (radial bit: r at or above the radial split of eq. (10), or of
 //     eq. (9) when the tree is set to equal areas; angular bit:
 //     phi >= (lo + hi) / 2), most significant level first;
@@ -11,10 +13,12 @@
 //  4. per sorted position: how many nodes start there (from the common
 //     prefixes with both neighbours), the sorted point record and the
 //     Einstein-midpoint summands, with block aggregates;
-//  5. exclusive scans (node offsets; double-double summand sums);
-//  6. node emission in depth-first pre-order: each node's first point, then
-//     per node its count, subtree end, leaf point or midpoint (eq. (11)) and
-//     cell diameter.
+//  5. exclusive scans (node offsets; double-double summand sums), after
+//     which every point records itself as the first point of the nodes it
+//     starts;
+//  6. node emission in depth-first pre-order, one thread per node: its
+//     count, subtree end, leaf point or midpoint (eq. (11)) and cell
+//     diameter.
 // A cell becomes a node when its parent holds two or more points (the same
 // set of cells the insertion build of Sec. 2-D produces), so no insertion
 // order is involved.
