@@ -53,6 +53,20 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+def build_caller(src: str, out: str, verbose: bool = False) -> str:
+    """A host program that calls the library through include/hts.h only."""
+    rel = os.path.relpath(HERE, os.path.dirname(os.path.abspath(out)))
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), src, "-o", out + ".tmp",
+           "-L", HERE, "-lhts", "-Wl,-rpath,$ORIGIN/" + rel]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-4000:]))
+    os.replace(out + ".tmp", out)
+    if verbose:
+        print("built", out)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
