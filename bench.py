@@ -289,6 +289,8 @@ def main():
                     help="also run a plain device copy of this size (for PMC calibration)")
     ap.add_argument("--split-rule", type=int, choices=[0, 1], default=0,
                     help="radial split: 0 equal lengths (eq. (10)), 1 equal areas (eq. (9))")
+    ap.add_argument("--item-list", type=int, default=None,
+                    help="item-list entries per phase-A wave (library default 256)")
     ap.add_argument("--hsne-lambda", type=float, default=None,
                     help="time the h-SNE iteration (Euclidean + lambda x hyperbolic term) instead")
     ap.add_argument("--workload", choices=["single", "jobs", "serve"], default="single",
@@ -326,6 +328,8 @@ def main():
     print("bench: generated X %dx%d in %.1fs" % (n, d, gen_s), file=sys.stderr, flush=True)
 
     ctx = hts.Context(0)
+    if args.item_list is not None:
+        ctx.set_item_list(args.item_list)
     Xd = torch.from_numpy(X).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -492,7 +496,7 @@ def main():
                                                             args.warmup + args.steps - 1),
                    "n": n, "d": d, "theta": args.theta, "perplexity": 30, "k": 90, "nnz": nnz,
                    "split_rule": "equal lengths, eq. (10)" if args.split_rule == 0
-                   else "equal areas, eq. (9)", "hsne_lambda": hs},
+                   else "equal areas, eq. (9)", "hsne_lambda": hs, "item_list": ctx.item_list},
         "exact_iters_per_s": round(exact_ips, 3) if exact_ips else None,
         "speedup_vs_exact": round(value / exact_ips, 1) if exact_ips else None,
         "kernel_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kt.items() if v[1]},

@@ -269,6 +269,16 @@ hts_status hts_jobs_schedule(hts_ctx ctx, hts_stream stream, int32_t n_jobs,
  * of floating-point sums.  Default 256; applies to later calls on ctx. */
 hts_status hts_set_item_points(hts_ctx ctx, int32_t item_points);
 
+/* Size of the list that carries those short walks between the two kernels of
+ * the traversal: each 64-query wave of the first kernel hands over at most
+ * items_per_wave (>= 0) of them (40 bytes and a 64-lane partial force each)
+ * and makes the others itself.  The split depends only on the wave, so every
+ * setting gives the same result up to the order of floating-point sums, and
+ * each setting gives it run after run; smaller lists use less device memory
+ * and run slower once waves exceed their share.  Default 256 (every walk a
+ * wave records); applies to later calls on ctx. */
+hts_status hts_set_item_list(hts_ctx ctx, int32_t items_per_wave);
+
 /* ------------------------------------------------------------------------
  * Kernel timing with HIP events on the caller's stream (for benchmarks).
  * While enabled, each launch of a timed kernel class is bracketed by events.

@@ -668,6 +668,14 @@ hts_status hts_set_item_points(hts_ctx c, int32_t item_points) {
     return HTS_OK;
 }
 
+hts_status hts_set_item_list(hts_ctx c, int32_t items_per_wave) {
+    if (!c) return fail(HTS_EINVAL, "hts_set_item_list: ctx is NULL");
+    if (items_per_wave < 0)
+        return fail(HTS_EINVAL, "hts_set_item_list: items_per_wave must be >= 0");
+    c->list_items = items_per_wave;
+    return HTS_OK;
+}
+
 // ---------------------------------------------------------------- timing
 hts_status hts_timing_enable(hts_ctx c, int32_t on) {
     if (!c) return fail(HTS_EINVAL, "hts_timing_enable: ctx is NULL");

@@ -90,6 +90,7 @@ struct Buffer {
 struct hts_ctx_s {
     int device = 0;
     int32_t item_points = 256;  // Barnes-Hut work-item size S (hts_set_item_points)
+    int32_t list_items = 256;   // item-list entries per phase-A wave (hts_set_item_list)
     uint32_t *d_err = nullptr;
     hts::Buffer pts, fattr, frep, zpart, part, spare;
     hts::Buffer aff[8];

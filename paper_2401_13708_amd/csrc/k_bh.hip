@@ -41,6 +41,9 @@ namespace hts {
 constexpr int kStats = 5;
 constexpr int kAttractLanes = 16;  // lanes per CSR row of the attractive term
 constexpr int kItemCap = 256;  // items one phase-A wave can hand to phase B
+// The item list holds ctx->list_items items per phase-A wave (kItemCap by
+// default: every item a wave records); a wave hands over at most that many
+// and walks the rest itself (see k_bh_top).
 constexpr int kTopDepth = 1;   // phase A splits each query block's walk at this depth ...
 constexpr int kTopSlots = 1 << (2 * kTopDepth);  // ... over this many waves
 
@@ -185,7 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     const int32_t *__restrict__ node_start, Jobs jb, const PointRec<T> *__restrict__ spts,
     int64_t nqb, int S, int *__restrict__ item_base, int *__restrict__ nitems_out,
     T *__restrict__ part0, double *__restrict__ ztop, uint32_t *__restrict__ stats_top,
-    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense, int64_t top_blocks,
+    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense, int share,
+    int64_t top_blocks,
     const PointRec<T> *__restrict__ pts, const int64_t *__restrict__ rp,
     const int32_t *__restrict__ col, const T *__restrict__ val, int64_t n, T *__restrict__ fattr,
     uint32_t *__restrict__ err) {
@@ -272,17 +276,32 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
         walk<T, MET, STATS, true>(nodes, M, spts, me, q, lane, a, nxa, da, m, S, items, nitems,
                                    fx, fy, z, c);
     }
-    // reserve a contiguous run of the item list (one atomic per wave; the
-    // runs of different waves may come in any order)
+    // hand over at most this wave's share of the item list (the share depends
+    // on nothing but the wave, so neither does the result); reserve a
+    // contiguous run for it (one atomic per wave; the runs of different waves
+    // may come in any order)
+    const int hand = nitems < share ? nitems : share;
     int base = 0;
-    if (lane == 0 && nitems > 0) base = (int)atomicAdd(dense_count, (unsigned)nitems);
+    if (lane == 0 && hand > 0) base = (int)atomicAdd(dense_count, (unsigned)hand);
     base = __shfl(base, 0, 64);
     // the records were written to LDS by lane 0 of this wave
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (int j = lane; j < nitems; j += kWave) {
+    for (int j = lane; j < hand; j += kWave) {
         const LdsItem it = items[j];
         dense[base + j] = ItemRec{it.node, it.nd, (int32_t)q0, cnt, it.mask, 0};
+    }
+    // items beyond the share: this wave makes the walks phase B would have made
+    // (same cells, same lanes, nothing more handed over)
+    int none = 0;
+    for (int j = hand; j < nitems; ++j) {
+        const LdsItem it = items[j];
+        const int node = uniform(it.node);
+        const uint32_t nd = (uint32_t)uniform((int)it.nd);
+        const uint64_t im = ((uint64_t)(uint32_t)uniform((int)(it.mask >> 32)) << 32) |
+                            (uint64_t)(uint32_t)uniform((int)it.mask);
+        walk<T, MET, STATS, false>(nodes, M, spts, me, q, lane, node + 1, (int)(nd & kNextMask),
+                                    (int)(nd >> kNextBits) + 1, im, 0, nullptr, none, fx, fy, z, c);
     }
     if (valid) {
         part0[((int64_t)slot * n + q) * 2] = fx;
@@ -292,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
     if (lane == 0) {
         ztop[g] = zs;
         item_base[g] = base;
-        nitems_out[g] = nitems;
+        nitems_out[g] = hand;
         put_stats<STATS>(stats_top + g * kStats, c);
     }
 }
@@ -341,11 +360,12 @@ template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_items(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
     const PointRec<T> *__restrict__ spts, const unsigned *__restrict__ dense_count,
-    const ItemRec *__restrict__ dense, T *__restrict__ part, double *__restrict__ zitem,
-    uint32_t *__restrict__ stats_items) {
+    const ItemRec *__restrict__ dense, int64_t cap, T *__restrict__ part,
+    double *__restrict__ zitem, uint32_t *__restrict__ stats_items) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int M = uniform(*d_m);
-    const int64_t total = (int64_t)uniform((int)*dense_count);
+    const int64_t reserved = (int64_t)(uint32_t)uniform((int)*dense_count);
+    const int64_t total = reserved < cap ? reserved : cap;  // never more, by the shares
     const int64_t G = (int64_t)gridDim.x * (kBlock / kWave);
     int dummy = 0;
     for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < total; i += G) {
@@ -525,7 +545,8 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const int64_t nqb = t->nqb;
     const Jobs jb = jobs_of(t);
     const int64_t nw = nqb * kTopSlots;  // phase-A waves
-    const int64_t slots = nw * kItemCap;
+    const int share = ctx->list_items < kItemCap ? ctx->list_items : kItemCap;
+    const int64_t slots = nw * share;
     const int S = ctx->item_points;
     // workspace: item list, partials, per-block sums
     const size_t b_base = (size_t)nw * 4, b_nit = (size_t)nw * 4;
@@ -562,6 +583,7 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const dim3 gq(cdiv(nqb, kBlock / kWave));
     int64_t gi = cdiv(slots, kBlock / kWave);
     if (gi > 16384) gi = 16384;  // several waves per SIMD slot: the hardware balances the load
+    if (gi < 1) gi = 1;          // an empty list (no items can be handed over)
     // one thread per point, and the node thresholds strided over the same grid
     const int64_t gp = cdiv(n, kBlock) > 64 ? cdiv(n, kBlock) : 64;
     hipLaunchKernelGGL(k_bh_prepare<T>, dim3(gp), dim3(kBlock), 0, st, prep.Y, n, pts, prep.points,
@@ -574,22 +596,22 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
         if (stats)
             hipLaunchKernelGGL((k_bh_top<T, MET, true>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
-                               st_top, dense_count, dense, top_blocks, pts, rp, col, val, n, fattr,
+                               st_top, dense_count, dense, share, top_blocks, pts, rp, col, val, n, fattr,
                                ctx->d_err);
         else
             hipLaunchKernelGGL((k_bh_top<T, MET, false>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
-                               nullptr, dense_count, dense, top_blocks, pts, rp, col, val, n,
+                               nullptr, dense_count, dense, share, top_blocks, pts, rp, col, val, n,
                                fattr, ctx->d_err);
     }
     {
         TimedScope ts(ctx, st, HTS_K_ITEMS);
         if (stats)
             hipLaunchKernelGGL((k_bh_items<T, MET, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
-                               spts, dense_count, dense, part, zitem, st_items);
+                               spts, dense_count, dense, slots, part, zitem, st_items);
         else
             hipLaunchKernelGGL((k_bh_items<T, MET, false>), dim3(gi), dim3(kBlock), 0, st, nodes,
-                               t->d_m, spts, dense_count, dense, part, zitem, nullptr);
+                               t->d_m, spts, dense_count, dense, slots, part, zitem, nullptr);
     }
     HTS_HIP(hipGetLastError());
     TimedScope ts(ctx, st, HTS_K_FINALIZE);

@@ -55,6 +55,7 @@ _SIGS = {
     "hts_step_jobs": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _I32, _P, _P, _D, _D, _I32]),
     "hts_jobs_schedule": (C.c_int, [_P, _P, _I32, _P, _I32, _D, _D, _D, _P, _P]),
     "hts_set_item_points": (C.c_int, [_P, _I32]),
+    "hts_set_item_list": (C.c_int, [_P, _I32]),
     "hts_cosne_terms": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _D, _D, _P]),
     "hts_tree_set_split": (C.c_int, [_P, _I32]),
     "hts_timing_enable": (C.c_int, [_P, _I32]),
@@ -121,6 +122,7 @@ def _dev(t: torch.Tensor, name: str, dtype=None):
 
 
 DEFAULT_ITEM_POINTS = 256  # the library's default work-item size
+DEFAULT_ITEM_LIST = 256    # the library's default item-list entries per phase-A wave
 
 
 class Context:
@@ -132,6 +134,7 @@ class Context:
         self.h = h
         self.device = device
         self.item_points = DEFAULT_ITEM_POINTS
+        self.item_list = DEFAULT_ITEM_LIST
 
     def close(self):
         if getattr(self, "h", None):
@@ -150,6 +153,11 @@ class Context:
         if code not in (0, -5):
             _ck(code)
         return int(bits.value)
+
+    def set_item_list(self, items_per_wave: int):
+        """Item-list entries per phase-A wave (device memory of the traversal)."""
+        _ck(lib().hts_set_item_list(self.h, int(items_per_wave)))
+        self.item_list = int(items_per_wave)
 
     def set_item_points(self, s: int):
         """Barnes-Hut work-item size (a tuning parameter)."""

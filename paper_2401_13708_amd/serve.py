@@ -53,14 +53,19 @@ class Result:
         return self.finished - self.arrival
 
 
-def footprint_bytes(n: int, k: int = 90, max_depth: int = 20) -> int:
+def footprint_bytes(n: int, k: int = 90, max_depth: int = 20,
+                    item_list: int = hts.DEFAULT_ITEM_LIST) -> int:
     """Device bytes a job of n points holds while it runs: P (at most 2nk
     entries of column + value, and row pointers), the state and gradient
-    arrays, its share of the tree storage and of the traversal workspace."""
+    arrays, its share of the tree storage and of the traversal workspace
+    (four phase-A waves per 64 queries, each with item_list item records of
+    40 bytes and 64-lane single-precision partials, plus per-slot partials of
+    every query)."""
     p = 2 * n * k * 8 + (n + 1) * 8
     state = n * 2 * 4 * 4
     tree = n * (max_depth + 1) * 56 + n * 120
-    trav = (n // 64 + 1) * 256 * (64 * 2 * 4 + 48)
+    waves = 4 * (n // 64 + 1)
+    trav = waves * (item_list * (64 * 2 * 4 + 40) + 16) + n * (4 * 2 * 4 + 2 * 4)
     return p + state + tree + trav
 
 
@@ -119,7 +124,7 @@ class Server:
             # admission in arrival order while the footprint fits (a job
             # larger than the whole budget runs alone)
             while waiting:
-                fp = footprint_bytes(waiting[0].X.shape[0], self.k, self.max_depth)
+                fp = footprint_bytes(waiting[0].X.shape[0], self.k, self.max_depth, self.ctx.item_list)
                 if active and used + fp > self.budget:
                     break
                 req = waiting.pop(0)

@@ -211,3 +211,35 @@ def test_bh_work_item_sizes(ctx, item_points):
     assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
     assert rel(g, go) < 1e-10
     assert z == pytest.approx(zo, rel=1e-10)
+
+
+@pytest.mark.parametrize("item_list", [0, 1, 3, 64])
+@pytest.mark.parametrize("item_points", [16, 256])
+def test_bh_item_list_sizes(ctx, item_list, item_points):
+    # a short item list: each phase-A wave hands over at most item_list walks
+    # and makes the rest itself (0: phase B gets nothing); the result, its
+    # counters and its run-to-run reproducibility do not depend on the split
+    X, _, rp, col, val = affinities(3000)
+    Y = embedding(3000, "late", np.float64)
+    ctx.set_item_points(item_points)
+    ctx.set_item_list(item_list)
+    try:
+        g, z, st = _run_bh(ctx, Y, rp, col, val, 12.0, 0.5, stats=True)
+        g2, z2 = _run_bh(ctx, Y, rp, col, val, 12.0, 0.5)
+    finally:
+        ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
+        ctx.set_item_list(hts.DEFAULT_ITEM_LIST)
+    t = oracle.Tree(Y)
+    go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 12.0)
+    assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    if item_list == 0:
+        assert st[5:] == [0, 0, 0, 0, 0]
+    assert rel(g, go) < 1e-10
+    assert z == pytest.approx(zo, rel=1e-10)
+    assert np.array_equal(g, g2) and z == z2
+
+
+def test_item_list_rejects_negative(ctx):
+    with pytest.raises(RuntimeError):
+        ctx.set_item_list(-1)
+    assert ctx.item_list == hts.DEFAULT_ITEM_LIST

@@ -240,3 +240,23 @@ def test_hsne_work_item_sizes_and_large_theta(ctx, item_points, theta):
     assert st[10:13] == [ch["tests"], ch["accepts"], ch["pairs"]]
     assert rel(g, go) < 1e-10
     assert z[0] == pytest.approx(ze, rel=1e-10)
+
+
+@pytest.mark.parametrize("item_list", [0, 2])
+def test_hsne_short_item_list(ctx, item_list):
+    # both traversals with waves that make most of their own item walks
+    X, _, rp, col, val = affinities(1500)
+    Y = embedding(1500, "late", np.float64)
+    ctx.set_item_points(16)
+    ctx.set_item_list(item_list)
+    try:
+        g, z, st = _run(ctx, Y, rp, col, val, 12.0, 0.6, 0.5, stats=True)
+    finally:
+        ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
+        ctx.set_item_list(hts.DEFAULT_ITEM_LIST)
+    go, ze, zh, ce, ch = _oracle(Y, rp, col, val, 12.0, 0.6, 0.5)
+    assert st[:3] == [ce["tests"], ce["accepts"], ce["pairs"]]
+    assert st[10:13] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    assert rel(g, go) < 1e-10
+    assert z[0] == pytest.approx(ze, rel=1e-10)
+    assert z[1] == pytest.approx(zh, rel=1e-10)
