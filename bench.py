@@ -289,6 +289,9 @@ def main():
                     help="also run a plain device copy of this size (for PMC calibration)")
     ap.add_argument("--split-rule", type=int, choices=[0, 1], default=0,
                     help="radial split: 0 equal lengths (eq. (10)), 1 equal areas (eq. (9))")
+    ap.add_argument("--write-native-input", metavar="PATH", default=None,
+                    help="write X and Y0 of the single workload for paper_2401_13708_amd/native/hts_run "
+                         "and exit (no GPU use)")
     ap.add_argument("--item-list", type=int, default=None,
                     help="item-list entries per phase-A wave (library default 256)")
     ap.add_argument("--hsne-lambda", type=float, default=None,
@@ -326,6 +329,13 @@ def main():
     Y0 = synth.disk_uniform(n, 1e-4, seed=2 + 10 ** 6)
     gen_s = time.perf_counter() - t0
     print("bench: generated X %dx%d in %.1fs" % (n, d, gen_s), file=sys.stderr, flush=True)
+    if args.write_native_input:
+        with open(args.write_native_input, "wb") as f:
+            f.write(np.array([n], np.int64).tobytes() + np.array([d, 0], np.int32).tobytes())
+            f.write(np.ascontiguousarray(X, np.float32).tobytes())
+            f.write(np.ascontiguousarray(Y0, np.float32).tobytes())
+        print("bench: wrote %s" % args.write_native_input, file=sys.stderr, flush=True)
+        return 0
 
     ctx = hts.Context(0)
     if args.item_list is not None:

@@ -54,9 +54,12 @@ def build(verbose: bool = False) -> str:
 
 
 def build_caller(src: str, out: str, verbose: bool = False) -> str:
-    """A host program that calls the library through include/hts.h only."""
+    """A program that calls the library through include/hts.h only (its own
+    kernels, if any, built for gfx950)."""
     rel = os.path.relpath(HERE, os.path.dirname(os.path.abspath(out)))
-    cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), src, "-o", out + ".tmp",
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), src, "-o", out + ".tmp",
            "-L", HERE, "-lhts", "-Wl,-rpath,$ORIGIN/" + rel]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

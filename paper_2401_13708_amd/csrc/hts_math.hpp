@@ -32,29 +32,33 @@ struct PairTerm {
     T vx, vy; // (q - o) + |q - o|^2 ia_q q
 };
 
-// distance argument in double from coordinates in T.  dd (2 qia) rounds to
-// the same value as (2 dd) qia (the factor 2 is exact), and 2 qia is the
-// same for every node a query meets, so it is formed once per walk.
+// distance argument in double from coordinates in T.  dq = dd (2 qia) rounds
+// to the same value as (2 dd) qia (the factor 2 is exact), and 2 qia is the
+// same for every node a query meets, so it is formed once per walk; dq / 2 is
+// |q - o|^2 ia_q exactly, the factor of q in eq. (13).
 template <typename T>
-__device__ __forceinline__ double dist_arg(T qx, T qy, double qia, T ox, T oy, double oib, double &dd) {
+__device__ __forceinline__ double dist_arg(T qx, T qy, double qia, T ox, T oy, double oib, double &dq) {
     double dx = (double)qx - (double)ox;
     double dy = (double)qy - (double)oy;
-    dd = dx * dx + dy * dy;
-    return dd * (2.0 * qia) * oib;
+    const double dd = dx * dx + dy * dy;
+    dq = dd * (2.0 * qia);
+    return dq * oib;
 }
 
-// double precision: library functions throughout
-template <typename T>
+// double precision: library functions throughout.  With QF = false the
+// query's own factor 4 ia_q is left out of `base` (a caller that sums many
+// terms of one query applies it once to the sum).
+template <typename T, bool QF = true>
 __device__ __forceinline__ PairTerm<T> pair_term(T qx, T qy, double qia, T ox, T oy, double oib,
-                                                 double t, double dd) {
+                                                 double t, double dq) {
     PairTerm<T> r;
     T tf = (T)t;
     T sh;
     T d = acosh1p(tf, sh);
     r.w = (T)1 / ((T)1 + d * d);
     T ratio = sh > (T)0 ? d / sh : (T)1;
-    r.base = ratio * (T)(4.0 * qia * oib);
-    T c = (T)(dd * qia);
+    r.base = QF ? ratio * (T)(4.0 * qia * oib) : ratio * (T)oib;
+    T c = (T)(0.5 * dq);
     r.vx = (qx - ox) + c * qx;
     r.vy = (qy - oy) + c * qy;
     return r;
@@ -66,10 +70,10 @@ __device__ __forceinline__ PairTerm<T> pair_term(T qx, T qy, double qia, T ox, T
 // up to t^6 leave a truncation error under 2e-9, and d = (d / sinh d) sinh d.
 // Above it, d = ln(1 + t + sinh d) is well conditioned (the argument exceeds
 // 1.6), so the hardware log2 / reciprocal / square root suffice.
-template <>
-__device__ __forceinline__ PairTerm<float> pair_term<float>(float qx, float qy, double qia, float ox,
-                                                            float oy, double oib, double t,
-                                                            double dd) {
+template <bool QF>
+__device__ __forceinline__ PairTerm<float> pair_term_f32(float qx, float qy, double qia, float ox,
+                                                         float oy, double oib, double t,
+                                                         double dq) {
     PairTerm<float> r;
     const float tf = (float)t;
     // one reciprocal square root gives 1 / sinh d; sinh d from it (0 for a
@@ -89,11 +93,25 @@ __device__ __forceinline__ PairTerm<float> pair_term<float>(float qx, float qy, 
     const float ratio = small ? qs : dl * rs;
     const float d = small ? qs * sh : dl;
     r.w = __builtin_amdgcn_rcpf(__builtin_fmaf(d, d, 1.0f));
-    r.base = ratio * (float)(4.0 * qia * oib);
-    const float c = (float)(dd * qia);
-    r.vx = (qx - ox) + c * qx;
-    r.vy = (qy - oy) + c * qy;
+    r.base = QF ? ratio * (float)(4.0 * qia * oib) : ratio * (float)oib;
+    // (float)(dq / 2) q = (float)dq (q / 2) exactly; q / 2 is the same for
+    // every term of a query
+    const float c = (float)dq;
+    r.vx = (qx - ox) + c * (0.5f * qx);
+    r.vy = (qy - oy) + c * (0.5f * qy);
     return r;
+}
+template <>
+__device__ __forceinline__ PairTerm<float> pair_term<float, true>(float qx, float qy, double qia,
+                                                                  float ox, float oy, double oib,
+                                                                  double t, double dq) {
+    return pair_term_f32<true>(qx, qy, qia, ox, oy, oib, t, dq);
+}
+template <>
+__device__ __forceinline__ PairTerm<float> pair_term<float, false>(float qx, float qy, double qia,
+                                                                   float ox, float oy, double oib,
+                                                                   double t, double dq) {
+    return pair_term_f32<false>(qx, qy, qia, ox, oy, oib, t, dq);
 }
 
 // ---------------------------------------------------------------- metrics
@@ -103,7 +121,10 @@ __device__ __forceinline__ PairTerm<float> pair_term<float>(float qx, float qy, 
 //          part of the h-SNE gradient, Sec. 3): w = (1 + |y - o|^2)^-1, terms
 //          w^m (y - o); the criterion argument is |y - o|^2 itself.
 // arg() returns the quantity compared with a node's threshold; attract() and
-// repel() add p w (...) and N w^2 (...) to the force and N w to Z.
+// repel() add p w (...) and N w^2 (...) to the force and N w to Z, except
+// that repel() leaves out a factor common to all terms of the query,
+// qfactor(), which the caller applies once to the query's summed repulsion.
+// The arguments dd of repel() and of arg() are what arg() hands back.
 template <int MET> struct Geo;
 
 template <> struct Geo<0> {
@@ -116,11 +137,16 @@ template <> struct Geo<0> {
     static __device__ __forceinline__ void repel(const PointRec<T> &me, T ox, T oy, double oib,
                                                  double t, double dd, T weight, T &fx, T &fy,
                                                  Z &z) {
-        const PairTerm<T> r = pair_term<T>(me.x, me.y, me.ia, ox, oy, oib, t, dd);
+        const PairTerm<T> r = pair_term<T, false>(me.x, me.y, me.ia, ox, oy, oib, t, dd);
         const T coef = weight * r.w * r.w * r.base;
         fx += coef * r.vx;
         fy += coef * r.vy;
         z += (Z)(weight * r.w);
+    }
+    // 4 ia_q of eq. (13)
+    template <typename T>
+    static __device__ __forceinline__ T qfactor(const PointRec<T> &me) {
+        return (T)(4.0 * me.ia);
     }
     template <typename T>
     static __device__ __forceinline__ T attract(const PointRec<T> &q, const PointRec<T> &o, T p,
@@ -160,6 +186,10 @@ template <> struct Geo<1> {
         fx += coef * (me.x - ox);
         fy += coef * (me.y - oy);
         z += (Z)(weight * w);
+    }
+    template <typename T>
+    static __device__ __forceinline__ T qfactor(const PointRec<T> &) {
+        return (T)1;
     }
     template <typename T>
     static __device__ __forceinline__ T attract(const PointRec<T> &q, const PointRec<T> &o, T p,

@@ -91,7 +91,8 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
         const int depth = (int)(nxd >> kNextBits);
         const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
-        const bool in = (m >> lane) & 1ull;
+        // the lanes of m as a lane predicate (the mask itself, no vector work)
+        const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
         const NodeRec<T> down = nodes[k + 1 < M ? k + 1 : k];
         const NodeRec<T> over = nodes[next < M ? next : k];
         if (STATS) c.step += 1;
@@ -130,11 +131,11 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             // is always in the mask here); only the term is masked
             double dd;
             const double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
-            const bool acc = in && t > cur.c;
-            if (acc) Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, zw);
-            const uint64_t rej = __ballot(in && !acc);
+            const uint64_t am = __builtin_amdgcn_ballot_w64(t > cur.c) & m;
+            if (__builtin_amdgcn_inverse_ballot_w64(am))
+                Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, zw);
+            const uint64_t rej = m & ~am;
             if (STATS) {
-                const uint64_t am = __ballot(acc);
                 c.test += __popcll(m);
                 c.acc += __popcll(am);
                 c.work += am != 0;
@@ -394,10 +395,11 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
 
 // Combine, stage 1: one wave per query block adds, slot by slot, the slot's
 // phase-A partial and then its items' partials in item order (eight loads in
-// flight at a time); the counters of the block are added to the caller's
-// totals.
-template <typename T, bool STATS>
+// flight at a time), then applies the query's common factor of the terms;
+// the counters of the block are added to the caller's totals.
+template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_gather(
+    const PointRec<T> *__restrict__ spts,
     const T *__restrict__ part0, const double *__restrict__ ztop, const T *__restrict__ part,
     const double *__restrict__ zitem, const int *__restrict__ item_base,
     const int *__restrict__ nitems_in, Jobs jb, int64_t nqb, int64_t n, T *__restrict__ frep,
@@ -458,8 +460,10 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
         }
     }
     if (valid) {
-        frep[2 * q] = fx;
-        frep[2 * q + 1] = fy;
+        // the query's common factor of the repulsive terms, once
+        const T f = Geo<MET>::qfactor(spts[q]);
+        frep[2 * q] = fx * f;
+        frep[2 * q + 1] = fy * f;
     }
     if (lane == 0) zq[qb] = zb;
     if (STATS) {
@@ -616,11 +620,11 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     HTS_HIP(hipGetLastError());
     TimedScope ts(ctx, st, HTS_K_FINALIZE);
     if (stats)
-        hipLaunchKernelGGL((k_bh_gather<T, true>), gq, dim3(kBlock), 0, st, part0, ztop, part,
+        hipLaunchKernelGGL((k_bh_gather<T, MET, true>), gq, dim3(kBlock), 0, st, spts, part0, ztop, part,
                            zitem, item_base, nitems, jb, nqb, n, frep, zq, st_top, st_items,
                            (unsigned long long *)stats);
     else
-        hipLaunchKernelGGL((k_bh_gather<T, false>), gq, dim3(kBlock), 0, st, part0, ztop, part,
+        hipLaunchKernelGGL((k_bh_gather<T, MET, false>), gq, dim3(kBlock), 0, st, spts, part0, ztop, part,
                            zitem, item_base, nitems, jb, nqb, n, frep, zq, nullptr, nullptr,
                            nullptr);
     hipLaunchKernelGGL(k_bh_finalize<T>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,

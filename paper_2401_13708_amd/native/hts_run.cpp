@@ -1,0 +1,230 @@
+// hts_run.cpp -- hyperbolic t-SNE iterations through the C ABI of
+// include/hts.h with no Python in the process: input affinities (Sec. 2-A,
+// eq. (1)) from X, then iterations of the Sec. 5 schedule (early
+// exaggeration 12 with momentum 0.5 for the first 250 iterations, then 1 and
+// 0.8; learning rate n / 12000; gains with floor 0.01), each one polar
+// quadtree build, one Barnes-Hut gradient (eqs. (15), (19)) and one
+// Riemannian step (eqs. (16)-(18)) on one stream with no host
+// synchronisation.  Prints one JSON line with the timing of the timed
+// iterations (HIP events on that stream).  With --copy-mib M it finally runs a
+// plain device copy of M MiB, a kernel of known traffic for reading hardware
+// byte counters against.
+//
+// usage: hts_run <input.bin> [--warmup W] [--steps K] [--theta T]
+//                [--item-list L] [--copy-mib M] [--out Y.bin] [--progress P]
+//   input.bin: int64 n, int32 d, int32 0, float X[n*d] (row-major),
+//              float Y0[2n] (the starting embedding in the Poincare disk)
+//   Y.bin:     float Y[2n] after the warm-up and timed iterations
+//   --progress P: a line on stderr every P iterations as they are issued
+//                 (for runs under a profiler that serialises launches)
+// Exit status 0 on success; otherwise the failing call is printed.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "hts.h"
+
+static void die(const char *what) {
+    std::fprintf(stderr, "hts_run: %s: %s\n", what, hts_last_error());
+    std::exit(1);
+}
+
+#define HIPCHK(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e__ = (call);                                                               \
+        if (e__ != hipSuccess) {                                                               \
+            std::fprintf(stderr, "hts_run: %s: %s\n", #call, hipGetErrorString(e__));        \
+            std::exit(1);                                                                      \
+        }                                                                                      \
+    } while (0)
+
+#define HTSCHK(call)                 \
+    do {                             \
+        if ((call) != HTS_OK) die(#call); \
+    } while (0)
+
+// 16-byte elements, grid-stride: reads and writes count * 16 bytes once each
+__global__ void copy_u4(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        dst[i] = src[i];
+}
+
+template <typename V>
+static void read_all(std::FILE *f, V *p, size_t count) {
+    if (std::fread(p, sizeof(V), count, f) != count) {
+        std::fprintf(stderr, "hts_run: short input file\n");
+        std::exit(1);
+    }
+}
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int main(int argc, char **argv) {
+    if (argc < 2) {
+        std::fprintf(stderr, "usage: hts_run <input.bin> [--warmup W] [--steps K] [--theta T] "
+                             "[--item-list L] [--copy-mib M] [--out Y.bin] [--progress P]\n");
+        return 2;
+    }
+    int warmup = 10, steps = 100, item_list = -1, progress = 0;
+    double theta = 0.5;
+    int64_t copy_mib = 0;
+    const char *out_path = nullptr;
+    for (int a = 2; a < argc; ++a) {
+        if (a + 1 >= argc) {
+            std::fprintf(stderr, "hts_run: %s needs a value\n", argv[a]);
+            return 2;
+        }
+        const char *v = argv[a + 1];
+        if (!std::strcmp(argv[a], "--warmup")) warmup = std::atoi(v);
+        else if (!std::strcmp(argv[a], "--steps")) steps = std::atoi(v);
+        else if (!std::strcmp(argv[a], "--theta")) theta = std::atof(v);
+        else if (!std::strcmp(argv[a], "--item-list")) item_list = std::atoi(v);
+        else if (!std::strcmp(argv[a], "--copy-mib")) copy_mib = std::atoll(v);
+        else if (!std::strcmp(argv[a], "--out")) out_path = v;
+        else if (!std::strcmp(argv[a], "--progress")) progress = std::atoi(v);
+        else {
+            std::fprintf(stderr, "hts_run: unknown option %s\n", argv[a]);
+            return 2;
+        }
+        ++a;
+    }
+    if (warmup < 0 || steps < 1 || copy_mib < 0) {
+        std::fprintf(stderr, "hts_run: need warmup >= 0, steps >= 1, copy-mib >= 0\n");
+        return 2;
+    }
+
+    std::FILE *in = std::fopen(argv[1], "rb");
+    if (!in) {
+        std::fprintf(stderr, "hts_run: cannot open %s\n", argv[1]);
+        return 1;
+    }
+    int64_t n = 0;
+    int32_t d = 0, zero = 0;
+    read_all(in, &n, 1);
+    read_all(in, &d, 1);
+    read_all(in, &zero, 1);
+    const int k = 90;
+    if (n <= k || d < 1 || zero != 0) {
+        std::fprintf(stderr, "hts_run: bad header (n %lld, d %d)\n", (long long)n, d);
+        return 1;
+    }
+    std::vector<float> X((size_t)n * d), Y0(2 * (size_t)n);
+    read_all(in, X.data(), X.size());
+    read_all(in, Y0.data(), Y0.size());
+    std::fclose(in);
+
+    hipStream_t st;
+    HIPCHK(hipStreamCreate(&st));
+    hts_ctx ctx = nullptr;
+    HTSCHK(hts_create(0, &ctx));
+    if (item_list >= 0) HTSCHK(hts_set_item_list(ctx, item_list));
+
+    // input affinities on the device
+    const int64_t cap = 2 * n * (int64_t)k;
+    float *dX, *dval;
+    int64_t *drp;
+    int32_t *dcol;
+    HIPCHK(hipMalloc(&dX, sizeof(float) * X.size()));
+    HIPCHK(hipMalloc(&drp, sizeof(int64_t) * (n + 1)));
+    HIPCHK(hipMalloc(&dcol, sizeof(int32_t) * cap));
+    HIPCHK(hipMalloc(&dval, sizeof(float) * cap));
+    HIPCHK(hipMemcpy(dX, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice));
+    int64_t nnz = 0;
+    double t0 = now_s();
+    HTSCHK(hts_build_affinities(ctx, st, dX, n, d, HTS_F32, 30.0, k, nullptr, drp, dcol, dval,
+                                HTS_F32, cap, &nnz));
+    const double aff_s = now_s() - t0;
+    HIPCHK(hipFree(dX));
+    std::fprintf(stderr, "hts_run: affinities nnz=%lld in %.2fs\n", (long long)nnz, aff_s);
+
+    // state: Y, update, gains, gradient, Z
+    float *dY, *dU, *dGain, *dG;
+    double *dz;
+    HIPCHK(hipMalloc(&dY, sizeof(float) * 2 * n));
+    HIPCHK(hipMalloc(&dU, sizeof(float) * 2 * n));
+    HIPCHK(hipMalloc(&dGain, sizeof(float) * 2 * n));
+    HIPCHK(hipMalloc(&dG, sizeof(float) * 2 * n));
+    HIPCHK(hipMalloc(&dz, sizeof(double)));
+    std::vector<float> zeros(2 * n, 0.0f), ones(2 * n, 1.0f);
+    HIPCHK(hipMemcpy(dY, Y0.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dU, zeros.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dGain, ones.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+    hts_tree tree = nullptr;
+    HTSCHK(hts_tree_create(ctx, n, 20, &tree));
+
+    const double eta = (double)n / 12000.0;
+    int it = 0;
+    auto iterate = [&]() {
+        const bool early = it < 250;
+        const double ex = early ? 12.0 : 1.0, mu = early ? 0.5 : 0.8;
+        HTSCHK(hts_build_polar_tree(ctx, st, dY, n, HTS_F32, tree));
+        HTSCHK(hts_gradient_bh(ctx, st, dY, n, HTS_F32, drp, dcol, dval, ex, tree, theta, dG, dz,
+                               nullptr));
+        HTSCHK(hts_step(ctx, st, dY, dU, dGain, dG, n, HTS_F32, eta, mu, 0.01, 1e-5, 2));
+        ++it;
+        if (progress > 0 && it % progress == 0) std::fprintf(stderr, "hts_run: iteration %d issued\n", it);
+    };
+    for (int w = 0; w < warmup; ++w) iterate();
+    uint32_t bits = 0;
+    HTSCHK(hts_check(ctx, st, &bits));
+    std::fprintf(stderr, "hts_run: %d warm-up iterations done\n", warmup);
+
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    t0 = now_s();
+    HIPCHK(hipEventRecord(e0, st));
+    for (int s = 0; s < steps; ++s) iterate();
+    HIPCHK(hipEventRecord(e1, st));
+    HTSCHK(hts_check(ctx, st, &bits));
+    const double wall = now_s() - t0;
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    std::printf("{\"n\": %lld, \"nnz\": %lld, \"theta\": %.3f, \"warmup\": %d, \"steps\": %d, "
+                "\"ms_per_step\": %.5f, \"iters_per_s\": %.2f, \"wall_s\": %.3f, "
+                "\"affinities_s\": %.3f}\n",
+                (long long)n, (long long)nnz, theta, warmup, steps, ms / steps, 1000.0 * steps / ms,
+                wall, aff_s);
+    std::fflush(stdout);
+    if (out_path) {
+        std::vector<float> Y(2 * n);
+        HIPCHK(hipMemcpy(Y.data(), dY, sizeof(float) * 2 * n, hipMemcpyDeviceToHost));
+        std::FILE *out = std::fopen(out_path, "wb");
+        if (!out || std::fwrite(Y.data(), sizeof(float), Y.size(), out) != Y.size()) {
+            std::fprintf(stderr, "hts_run: cannot write %s\n", out_path);
+            return 1;
+        }
+        std::fclose(out);
+    }
+
+    if (copy_mib > 0) {
+        const int64_t count = copy_mib * (1 << 20) / 16;
+        uint4 *a, *b;
+        HIPCHK(hipMalloc(&a, (size_t)count * 16));
+        HIPCHK(hipMalloc(&b, (size_t)count * 16));
+        HIPCHK(hipMemsetAsync(a, 0, (size_t)count * 16, st));
+        hipLaunchKernelGGL(copy_u4, dim3(4096), dim3(256), 0, st, a, b, count);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        std::fprintf(stderr, "hts_run: copied %lld MiB\n", (long long)copy_mib);
+        HIPCHK(hipFree(a));
+        HIPCHK(hipFree(b));
+    }
+
+    HTSCHK(hts_tree_destroy(tree));
+    HTSCHK(hts_destroy(ctx));
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    HIPCHK(hipStreamDestroy(st));
+    for (void *p : {(void *)drp, (void *)dcol, (void *)dval, (void *)dY, (void *)dU, (void *)dGain,
+                    (void *)dG, (void *)dz})
+        HIPCHK(hipFree(p));
+    return 0;
+}
