@@ -291,7 +291,10 @@ def main():
                     help="radial split: 0 equal lengths (eq. (10)), 1 equal areas (eq. (9))")
     ap.add_argument("--write-native-input", metavar="PATH", default=None,
                     help="write X and Y0 of the single workload for paper_2401_13708_amd/native/hts_run "
-                         "and exit (no GPU use)")
+                         "and exit (no GPU use unless --native-start-iteration is given)")
+    ap.add_argument("--native-start-iteration", type=int, default=0,
+                    help="with --write-native-input: run this many iterations on the GPU first and "
+                         "write the embedding reached (the native run continues the schedule there)")
     ap.add_argument("--item-list", type=int, default=None,
                     help="item-list entries per phase-A wave (library default 256)")
     ap.add_argument("--hsne-lambda", type=float, default=None,
@@ -330,11 +333,21 @@ def main():
     gen_s = time.perf_counter() - t0
     print("bench: generated X %dx%d in %.1fs" % (n, d, gen_s), file=sys.stderr, flush=True)
     if args.write_native_input:
+        it0 = args.native_start_iteration
+        Ys = Y0
+        if it0 > 0:
+            ctx = hts.Context(0)
+            _, rp, col, val = hts.build_affinities(ctx, torch.from_numpy(X).to(dev), 30.0, 90,
+                                                   p_dtype=torch.float32, want_knn=False)
+            emb = Embedding(ctx, rp, col, val, torch.from_numpy(Y0).to(dev), theta=args.theta)
+            emb.run(it0)
+            torch.cuda.synchronize()
+            Ys = emb.Y.cpu().numpy()
         with open(args.write_native_input, "wb") as f:
-            f.write(np.array([n], np.int64).tobytes() + np.array([d, 0], np.int32).tobytes())
+            f.write(np.array([n], np.int64).tobytes() + np.array([d, it0], np.int32).tobytes())
             f.write(np.ascontiguousarray(X, np.float32).tobytes())
-            f.write(np.ascontiguousarray(Y0, np.float32).tobytes())
-        print("bench: wrote %s" % args.write_native_input, file=sys.stderr, flush=True)
+            f.write(np.ascontiguousarray(Ys, np.float32).tobytes())
+        print("bench: wrote %s (iteration %d)" % (args.write_native_input, it0), file=sys.stderr, flush=True)
         return 0
 
     ctx = hts.Context(0)

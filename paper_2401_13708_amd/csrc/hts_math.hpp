@@ -76,11 +76,12 @@ __device__ __forceinline__ PairTerm<float> pair_term_f32(float qx, float qy, dou
                                                          double dq) {
     PairTerm<float> r;
     const float tf = (float)t;
-    // one reciprocal square root gives 1 / sinh d; sinh d from it (0 for a
-    // vanishing argument, where the reciprocal is infinite)
+    // one reciprocal square root gives 1 / sinh d, and sinh d = x / sqrt(x).
+    // The argument is kept >= 1e-30 so that x = 0 gives sinh d = 0; below
+    // 1e-30, sinh d < 1e-15 either way and d^2 vanishes next to 1.
     const float x = tf * (tf + 2.0f);
-    const float rs = __builtin_amdgcn_rsqf(x);
-    const float sh = x > 1e-30f ? x * rs : 0.0f;
+    const float rs = __builtin_amdgcn_rsqf(__builtin_fmaxf(x, 1e-30f));
+    const float sh = x * rs;
     float qs = 16.0f / 3003.0f;
     qs = __builtin_fmaf(qs, tf, -8.0f / 693.0f);
     qs = __builtin_fmaf(qs, tf, 8.0f / 315.0f);

@@ -12,8 +12,9 @@
 //
 // usage: hts_run <input.bin> [--warmup W] [--steps K] [--theta T]
 //                [--item-list L] [--copy-mib M] [--out Y.bin] [--progress P]
-//   input.bin: int64 n, int32 d, int32 0, float X[n*d] (row-major),
-//              float Y0[2n] (the starting embedding in the Poincare disk)
+//   input.bin: int64 n, int32 d, int32 it0, float X[n*d] (row-major),
+//              float Y0[2n] (the embedding in the Poincare disk at iteration
+//              it0 of the schedule, where the run starts; update 0, gains 1)
 //   Y.bin:     float Y[2n] after the warm-up and timed iterations
 //   --progress P: a line on stderr every P iterations as they are issued
 //                 (for runs under a profiler that serialises launches)
@@ -106,12 +107,12 @@ int main(int argc, char **argv) {
         return 1;
     }
     int64_t n = 0;
-    int32_t d = 0, zero = 0;
+    int32_t d = 0, it0 = 0;
     read_all(in, &n, 1);
     read_all(in, &d, 1);
-    read_all(in, &zero, 1);
+    read_all(in, &it0, 1);
     const int k = 90;
-    if (n <= k || d < 1 || zero != 0) {
+    if (n <= k || d < 1 || it0 < 0) {
         std::fprintf(stderr, "hts_run: bad header (n %lld, d %d)\n", (long long)n, d);
         return 1;
     }
@@ -160,7 +161,7 @@ int main(int argc, char **argv) {
     HTSCHK(hts_tree_create(ctx, n, 20, &tree));
 
     const double eta = (double)n / 12000.0;
-    int it = 0;
+    int it = it0;
     auto iterate = [&]() {
         const bool early = it < 250;
         const double ex = early ? 12.0 : 1.0, mu = early ? 0.5 : 0.8;
@@ -187,11 +188,11 @@ int main(int argc, char **argv) {
     const double wall = now_s() - t0;
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    std::printf("{\"n\": %lld, \"nnz\": %lld, \"theta\": %.3f, \"warmup\": %d, \"steps\": %d, "
-                "\"ms_per_step\": %.5f, \"iters_per_s\": %.2f, \"wall_s\": %.3f, "
-                "\"affinities_s\": %.3f}\n",
-                (long long)n, (long long)nnz, theta, warmup, steps, ms / steps, 1000.0 * steps / ms,
-                wall, aff_s);
+    std::printf("{\"n\": %lld, \"nnz\": %lld, \"theta\": %.3f, \"start_iteration\": %d, "
+                "\"warmup\": %d, \"steps\": %d, \"ms_per_step\": %.5f, \"iters_per_s\": %.2f, "
+                "\"wall_s\": %.3f, \"affinities_s\": %.3f}\n",
+                (long long)n, (long long)nnz, theta, it0, warmup, steps, ms / steps,
+                1000.0 * steps / ms, wall, aff_s);
     std::fflush(stdout);
     if (out_path) {
         std::vector<float> Y(2 * n);

@@ -21,15 +21,18 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 BIN = os.path.join(ROOT, "paper_2401_13708_amd", "native", "hts_run")
 
 
-@pytest.mark.parametrize("n,d,warmup,steps,item_list", [(3000, 24, 3, 5, -1), (1777, 10, 248, 4, 2)])
-def test_native_driver_equals_python_driver(ctx, tmp_path, n, d, warmup, steps, item_list):
+@pytest.mark.parametrize("n,d,it0,warmup,steps,item_list",
+                         [(3000, 24, 0, 3, 5, -1), (1777, 10, 0, 248, 4, 2), (2100, 12, 247, 1, 4, -1)])
+def test_native_driver_equals_python_driver(ctx, tmp_path, n, d, it0, warmup, steps, item_list):
     if not os.path.exists(BIN):
         pytest.fail("the native driver is not built (__graft_entry__.build() builds it)")
     src, dst = tmp_path / "in.bin", tmp_path / "y.bin"
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--n", str(n), "--d", str(d),
-                        "--write-native-input", str(src)], capture_output=True, text=True, timeout=120)
+                        "--write-native-input", str(src), "--native-start-iteration", str(it0)],
+                       capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     raw = open(src, "rb").read()
+    assert np.frombuffer(raw[8:16], np.int32).tolist() == [d, it0]
     X = np.frombuffer(raw[16:16 + 4 * n * d], np.float32).reshape(n, d)
     Y0 = np.frombuffer(raw[16 + 4 * n * d:], np.float32).reshape(n, 2)
     cmd = [BIN, str(src), "--warmup", str(warmup), "--steps", str(steps), "--out", str(dst)]
@@ -49,7 +52,10 @@ def test_native_driver_equals_python_driver(ctx, tmp_path, n, d, warmup, steps, 
     if item_list >= 0:
         ctx.set_item_list(item_list)
     try:
+        # the native run starts at iteration it0 of the schedule from the
+        # stored embedding, with update 0 and gains 1
         emb = Embedding(ctx, rp, col, val, torch.from_numpy(Y0.copy()).to(dev), theta=0.5)
+        emb.it = it0
         emb.run(warmup + steps)
         torch.cuda.synchronize()
     finally:
