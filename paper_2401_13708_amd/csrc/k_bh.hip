@@ -85,50 +85,24 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
     int mhi = lane == d0 ? (int)(uint32_t)(mask0 >> 32) : 0;
     NodeRec<T> nrec = nodes[k < M ? k : M - 1];
     while (k < kend) {
-        const NodeRec<T> cur = nrec;
-        const uint32_t nxd = (uint32_t)uniform((int)cur.next_depth);
-        const int next = (int)(nxd & kNextMask);
-        const int depth = (int)(nxd >> kNextBits);
-        const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
-                           (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
-        // the lanes of m as a lane predicate (the mask itself, no vector work)
-        const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
-        const NodeRec<T> down = nodes[k + 1 < M ? k + 1 : k];
-        const NodeRec<T> over = nodes[next < M ? next : k];
-        if (STATS) c.step += 1;
-        if (next == k + 1) {
-            // leaf: exact terms with each of its points, skipping the query
-            const int64_t first = (int64_t)__double_as_longlong(cur.c);
-            const int cnt = uniform(cur.count);
-            if (cnt == 1) {
-                const bool use = in && first != q;
-                if (use) {
-                    double dd;
-                    double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
-                    Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, zw);
-                }
-                if (STATS) {
-                    const uint64_t um = __ballot(use);
-                    c.pair += __popcll(um);
-                    c.work += um != 0;
-                }
-            } else {
-                for (int a = 0; a < cnt; ++a) {
-                    const PointRec<T> o = spts[first + a];
-                    const bool use = in && (first + a) != q;
-                    if (use) {
-                        double dd;
-                        double t = Geo<MET>::arg(me, o.x, o.y, o.ia, dd);
-                        Geo<MET>::repel(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, zw);
-                    }
-                    if (STATS) c.pair += __popcll(__ballot(use));
-                }
-            }
-            k = next;
-            nrec = over;
-        } else {
+        NodeRec<T> cur = nrec;
+        uint32_t nxd = (uint32_t)uniform((int)cur.next_depth);
+        int next = (int)(nxd & kNextMask);
+        // internal nodes, until the walk meets a leaf or leaves its range
+        while (next != k + 1) {
+            const int depth = (int)(nxd >> kNextBits);
+            const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
+                               (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
+            // the next sibling's record is loaded before the test and the term
+            // (the compiler barrier keeps the load from sinking to its use), the
+            // first child's only when the walk descends
+            const NodeRec<T> over = nodes[next < M ? next : k];
+            asm volatile("" ::: "memory");
+            if (STATS) c.step += 1;
             // the test costs the same for every lane (some lane of the wave
-            // is always in the mask here); only the term is masked
+            // is always in the mask here); only the term is masked, by the
+            // lanes of m that accept (the masks serve as lane predicates
+            // directly, with no vector work)
             double dd;
             const double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
             const uint64_t am = __builtin_amdgcn_ballot_w64(t > cur.c) & m;
@@ -149,13 +123,53 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 const bool here = lane == depth + 1;
                 mlo = here ? (int)(uint32_t)rej : mlo;
                 mhi = here ? (int)(uint32_t)(rej >> 32) : mhi;
+                nrec = nodes[k + 1 < M ? k + 1 : k];
                 k = k + 1;
-                nrec = down;
             } else {
                 k = next;
                 nrec = over;
             }
+            if (k >= kend) break;
+            cur = nrec;
+            nxd = (uint32_t)uniform((int)cur.next_depth);
+            next = (int)(nxd & kNextMask);
         }
+        if (k >= kend) break;
+        // leaf: exact terms with each of its points, skipping the query
+        const int depth = (int)(nxd >> kNextBits);
+        const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
+                           (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
+        const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
+        const NodeRec<T> over = nodes[next < M ? next : k];
+        if (STATS) c.step += 1;
+        const int64_t first = (int64_t)__double_as_longlong(cur.c);
+        const int cnt = uniform(cur.count);
+        if (cnt == 1) {
+            const bool use = in && first != q;
+            if (use) {
+                double dd;
+                double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
+                Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, zw);
+            }
+            if (STATS) {
+                const uint64_t um = __ballot(use);
+                c.pair += __popcll(um);
+                c.work += um != 0;
+            }
+        } else {
+            for (int a = 0; a < cnt; ++a) {
+                const PointRec<T> o = spts[first + a];
+                const bool use = in && (first + a) != q;
+                if (use) {
+                    double dd;
+                    double t = Geo<MET>::arg(me, o.x, o.y, o.ia, dd);
+                    Geo<MET>::repel(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, zw);
+                }
+                if (STATS) c.pair += __popcll(__ballot(use));
+            }
+        }
+        k = next;
+        nrec = over;
     }
     z += (double)zw;
 }
