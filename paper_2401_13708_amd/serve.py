@@ -57,16 +57,20 @@ def footprint_bytes(n: int, k: int = 90, max_depth: int = 20,
                     item_list: int = hts.DEFAULT_ITEM_LIST) -> int:
     """Device bytes a job of n points holds while it runs: P (at most 2nk
     entries of column + value, and row pointers), the state and gradient
-    arrays, its share of the tree storage and of the traversal workspace
-    (four phase-A waves per 64 queries, each with item_list item records of
-    40 bytes and 64-lane single-precision partials, plus per-slot partials of
-    every query)."""
+    arrays, its share of the tree storage (60 bytes per node slot, n (depth
+    + 1) slots, and 142 bytes per point of keys, sort buffers, prefix sums and
+    point records), the per-point buffers of the gradient call, its share of
+    the traversal workspace (four phase-A waves per 64 queries, each with
+    item_list item records of 40 bytes and 64-lane single-precision partials,
+    plus per-slot partials of every query), and 8 MiB for allocation
+    granularity."""
     p = 2 * n * k * 8 + (n + 1) * 8
     state = n * 2 * 4 * 4
-    tree = n * (max_depth + 1) * 56 + n * 120
+    tree = n * (max_depth + 1) * 60 + n * 142
+    grad = n * 40
     waves = 4 * (n // 64 + 1)
     trav = waves * (item_list * (64 * 2 * 4 + 40) + 16) + n * (4 * 2 * 4 + 2 * 4)
-    return p + state + tree + trav
+    return p + state + tree + grad + trav + (8 << 20)
 
 
 def _start_embedding(n: int, seed: int, dev) -> torch.Tensor:

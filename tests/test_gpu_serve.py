@@ -46,3 +46,35 @@ def test_budget_smaller_than_a_job_serves_one_at_a_time(ctx):
     srv = Server(ctx, 1, schedule=sched)
     out = srv.run(reqs)
     assert srv.max_active == 1 and len(out) == 3
+
+
+def test_footprint_covers_a_running_job():
+    # the admission estimate bounds what one job's iterations add on the
+    # device beyond its P: tree storage, traversal workspace and state
+    # (measured on a fresh context, after P is built)
+    from paper_2401_13708_amd import hts
+    from paper_2401_13708_amd.embed import Embedding
+    n, k = 20000, 90
+    c = hts.Context(0)
+    try:
+        X = torch.from_numpy(synth.gaussian_mixture(n, 16, seed=9)).float().cuda()
+        _, rp, col, val = hts.build_affinities(c, X, 30.0, k, p_dtype=torch.float32, want_knn=False)
+        del X
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free0 = torch.cuda.mem_get_info()[0]
+        Y0 = torch.from_numpy(synth.disk_uniform(n, 1e-4, seed=4)).cuda()
+        emb = Embedding(c, rp, col, val, Y0, theta=0.5)
+        emb.run(300)     # past early exaggeration: the walks and their item lists have grown
+        torch.cuda.synchronize()
+        assert c.check() == 0
+        used = free0 - torch.cuda.mem_get_info()[0]
+        p_bytes = rp.numel() * 8 + col.numel() * 4 + val.numel() * 4
+        est = footprint_bytes(n, k, 20, c.item_list) - p_bytes
+        print("n", n, "used", used, "estimate beyond P", est, flush=True)
+        assert used <= est, (used, est)
+        # and it is not a loose bound: the traversal workspace dominates both
+        assert used >= 0.6 * est, (used, est)
+        emb.close()
+    finally:
+        c.close()
