@@ -10,9 +10,10 @@
 // set of lanes that need the children.  Leaves are evaluated exactly, skipping
 // the query.  The lanes that need a subtree form a 64-bit mask per depth, kept
 // in two VGPRs used as lane-indexed arrays (readlane with the depth to read,
-// a lane select to write).  Node records are read with scalar loads, both
-// possible successors (first child, next sibling) in flight while a node is
-// evaluated; enough waves per SIMD hide their latency.
+// a lane select to write), and a mask serves directly as the lane predicate
+// of the masked term.  Node records are read with scalar loads; the next
+// sibling's is in flight while a node is evaluated, the first child's is
+// loaded when the walk descends, and enough waves per SIMD hide the latency.
 //
 // One wave walking the whole tree for its block is a long serial chain, so the
 // walk is split in two phases:
@@ -72,8 +73,9 @@ struct Counters {
 // internal node of at most S points that some lanes reject is appended to the
 // wave's item list (while there is room) instead of being descended.  The
 // walk's Z terms are summed in T and added to z once at the end.
-// Node records are read with scalar loads (the node index is uniform);
-// both possible successors are fetched while a node is evaluated.
+// Node records are read with scalar loads (the node index is uniform).
+// Internal nodes are walked in an inner loop and each leaf in the outer one,
+// so the accumulators keep their registers across the masked terms.
 template <typename T, int MET, bool STATS, bool EMIT>
 __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M,
                                      const PointRec<T> *__restrict__ spts, const PointRec<T> &me,
