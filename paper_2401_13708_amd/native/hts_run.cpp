@@ -10,7 +10,8 @@
 // plain device copy of M MiB, a kernel of known traffic for reading hardware
 // byte counters against.
 //
-// usage: hts_run <input.bin> [--warmup W] [--steps K] [--theta T]
+// usage: hts_run --peaks     (attainable copy bandwidth and vector FMA rates)
+//        hts_run <input.bin> [--warmup W] [--steps K] [--theta T]
 //                [--item-list L] [--copy-mib M] [--out Y.bin] [--progress P]
 //   input.bin: int64 n, int32 d, int32 it0, float X[n*d] (row-major),
 //              float Y0[2n] (the embedding in the Poincare disk at iteration
@@ -55,6 +56,81 @@ __global__ void copy_u4(const uint4 *__restrict__ src, uint4 *__restrict__ dst, 
         dst[i] = src[i];
 }
 
+// kFmaChains independent multiply-add chains per thread, kFmaSteps steps each:
+// 2 * kFmaChains * kFmaSteps flops per thread at the vector unit's rate
+constexpr int kFmaChains = 8, kFmaSteps = 2048;
+template <typename F>
+__global__ void fma_chains(F b, F c, F *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    F a[kFmaChains];
+#pragma unroll
+    for (int j = 0; j < kFmaChains; ++j) a[j] = (F)(i & 7) + (F)j;
+    for (int s = 0; s < kFmaSteps; ++s)
+#pragma unroll
+        for (int j = 0; j < kFmaChains; ++j) a[j] = a[j] * b + c;
+    F r = 0;
+#pragma unroll
+    for (int j = 0; j < kFmaChains; ++j) r += a[j];
+    out[i] = r;
+}
+
+// Attainable rates of this device: a 1 GiB device copy (HBM bytes read +
+// written per second) and the FP32 / FP64 vector multiply-add rate (no
+// packed FP32); the best of five timed runs of each, one JSON line.
+static int run_peaks() {
+    hipStream_t st;
+    HIPCHK(hipStreamCreate(&st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto best_ms = [&](auto launch) {
+        float best = 1e30f;
+        launch();  // warm-up
+        for (int r = 0; r < 5; ++r) {
+            HIPCHK(hipEventRecord(e0, st));
+            launch();
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) best = ms;
+        }
+        return (double)best;
+    };
+    const int64_t count = ((int64_t)1 << 30) / 16;
+    uint4 *a, *b;
+    HIPCHK(hipMalloc(&a, (size_t)count * 16));
+    HIPCHK(hipMalloc(&b, (size_t)count * 16));
+    HIPCHK(hipMemsetAsync(a, 0, (size_t)count * 16, st));
+    const double copy_ms = best_ms([&]() {
+        hipLaunchKernelGGL(copy_u4, dim3(8192), dim3(256), 0, st, a, b, count);
+    });
+    HIPCHK(hipGetLastError());
+    const int blocks = 8192, threads = 256;
+    float *of;
+    double *od;
+    HIPCHK(hipMalloc(&of, sizeof(float) * blocks * threads));
+    HIPCHK(hipMalloc(&od, sizeof(double) * blocks * threads));
+    const double f32_ms = best_ms([&]() {
+        hipLaunchKernelGGL(fma_chains<float>, dim3(blocks), dim3(threads), 0, st, 0.999f, 0.001f, of);
+    });
+    const double f64_ms = best_ms([&]() {
+        hipLaunchKernelGGL(fma_chains<double>, dim3(blocks), dim3(threads), 0, st, 0.999, 0.001, od);
+    });
+    HIPCHK(hipGetLastError());
+    const double flops = 2.0 * kFmaChains * kFmaSteps * (double)blocks * threads;
+    std::printf("{\"copy_GBps\": %.1f, \"fp32_fma_TFLOPs\": %.2f, \"fp64_fma_TFLOPs\": %.2f, "
+                "\"copy_bytes\": %lld, \"copy_ms\": %.4f, \"fma_flops\": %.0f, \"fp32_ms\": %.4f, "
+                "\"fp64_ms\": %.4f}\n",
+                2.0 * count * 16 / (copy_ms * 1e6), flops / (f32_ms * 1e9), flops / (f64_ms * 1e9),
+                (long long)(2 * count * 16), copy_ms, flops, f32_ms, f64_ms);
+    for (void *p : {(void *)a, (void *)b, (void *)of, (void *)od}) HIPCHK(hipFree(p));
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    HIPCHK(hipStreamDestroy(st));
+    return 0;
+}
+
 template <typename V>
 static void read_all(std::FILE *f, V *p, size_t count) {
     if (std::fread(p, sizeof(V), count, f) != count) {
@@ -68,6 +144,7 @@ static double now_s() {
 }
 
 int main(int argc, char **argv) {
+    if (argc == 2 && !std::strcmp(argv[1], "--peaks")) return run_peaks();
     if (argc < 2) {
         std::fprintf(stderr, "usage: hts_run <input.bin> [--warmup W] [--steps K] [--theta T] "
                              "[--item-list L] [--copy-mib M] [--out Y.bin] [--progress P]\n");
