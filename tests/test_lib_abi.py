@@ -63,3 +63,39 @@ def test_host_validation(call, msg):
     rc = call(L)
     assert rc == -1
     assert msg in hts.last_error()
+
+
+def test_item_list_share_needs_a_context():
+    # argument check on the host, before any device work (the negative share
+    # is refused in tests/test_gpu_gradient.py, which has a context)
+    L = hts.lib()
+    assert L.hts_set_item_list(None, 5) != 0
+    assert "ctx is NULL" in hts.last_error()
+
+
+def test_native_driver_input_file(tmp_path):
+    # bench.py writes the native driver's input: header (n, d, start
+    # iteration) and the same seeded X and starting embedding the bench uses
+    import numpy as np
+    from paper_2401_13708_amd import synth
+    path = tmp_path / "in.bin"
+    r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--n", "300", "--d", "5",
+                        "--write-native-input", str(path)], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    raw = path.read_bytes()
+    assert np.frombuffer(raw[:8], np.int64)[0] == 300
+    assert np.frombuffer(raw[8:16], np.int32).tolist() == [5, 0]
+    assert len(raw) == 16 + 4 * 300 * 5 + 4 * 300 * 2
+    X = np.frombuffer(raw[16:16 + 4 * 1500], np.float32).reshape(300, 5)
+    Y = np.frombuffer(raw[16 + 4 * 1500:], np.float32).reshape(300, 2)
+    assert np.array_equal(X, synth.sigmoid_factor_mixture(300, 5, seed=2).astype(np.float32))
+    assert np.array_equal(Y, synth.disk_uniform(300, 1e-4, seed=2 + 10 ** 6).astype(np.float32))
+
+
+def test_native_driver_is_built_for_gfx950():
+    exe = os.path.join(ROOT, "paper_2401_13708_amd", "native", "hts_run")
+    assert os.path.exists(exe), "the native driver is not built (__graft_entry__.build() builds it)"
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage" in r.stderr
+    assert b"amdgcn-amd-amdhsa--gfx950" in open(exe, "rb").read()
