@@ -276,7 +276,7 @@ hts_status hts_set_item_points(hts_ctx ctx, int32_t item_points);
  * setting gives the same result up to the order of floating-point sums, and
  * each setting gives it run after run; smaller lists use less device memory
  * and run slower once waves exceed their share.  Default 256 (every walk a
- * wave records); applies to later calls on ctx. */
+ * wave records; larger values act as 256); applies to later calls on ctx. */
 hts_status hts_set_item_list(hts_ctx ctx, int32_t items_per_wave);
 
 /* ------------------------------------------------------------------------
