@@ -93,8 +93,21 @@ def _single_bh(ctx, Yj, rp, col, val, ex, theta):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-@pytest.mark.parametrize("theta", [0.5, 0.0])
-def test_job_gradients_match_single(ctx, dtype, theta):
+@pytest.mark.parametrize("theta,item_list", [(0.5, None), (0.0, None), (0.5, 1)])
+def test_job_gradients_match_single(ctx, dtype, theta, item_list):
+    # with a one-item share per phase-A wave as well: the waves of a job are
+    # the same in the layout and alone, so are their splits
+    if item_list is not None:
+        ctx.set_item_points(16)
+        ctx.set_item_list(item_list)
+    try:
+        _job_gradients_match_single(ctx, dtype, theta)
+    finally:
+        ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
+        ctx.set_item_list(hts.DEFAULT_ITEM_LIST)
+
+
+def _job_gradients_match_single(ctx, dtype, theta):
     parts = _jobs(dtype)
     Y, rp, col, val = _concat(parts)
     exs = np.array([12.0 if j % 2 else 1.0 for j in range(len(SIZES))])
