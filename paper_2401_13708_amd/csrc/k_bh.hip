@@ -75,7 +75,10 @@ struct Counters {
 // walk's Z terms are summed in T and added to z once at the end.
 // Node records are read with scalar loads (the node index is uniform).
 // Internal nodes are walked in an inner loop and each leaf in the outer one,
-// so the accumulators keep their registers across the masked terms.
+// so the accumulators keep their registers across the masked terms.  A
+// successor index is at most M, and the node arrays hold more than M records
+// (their capacity n_max (depth cap + 1) + 1 exceeds any node count), so the
+// successor of the last node is a readable record that is never used.
 template <typename T, int MET, bool STATS, bool EMIT>
 __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M,
                                      const PointRec<T> *__restrict__ spts, const PointRec<T> &me,
@@ -98,7 +101,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             // the next sibling's record is loaded before the test and the term
             // (the compiler barrier keeps the load from sinking to its use), the
             // first child's only when the walk descends
-            const NodeRec<T> over = nodes[next < M ? next : k];
+            const NodeRec<T> over = nodes[(uint32_t)next];
             asm volatile("" ::: "memory");
             if (STATS) c.step += 1;
             // the test costs the same for every lane (some lane of the wave
@@ -125,7 +128,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 const bool here = lane == depth + 1;
                 mlo = here ? (int)(uint32_t)rej : mlo;
                 mhi = here ? (int)(uint32_t)(rej >> 32) : mhi;
-                nrec = nodes[k + 1 < M ? k + 1 : k];
+                nrec = nodes[(uint32_t)(k + 1)];
                 k = k + 1;
             } else {
                 k = next;
@@ -142,7 +145,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
         const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
         const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
-        const NodeRec<T> over = nodes[next < M ? next : k];
+        const NodeRec<T> over = nodes[(uint32_t)next];
         if (STATS) c.step += 1;
         const int64_t first = (int64_t)__double_as_longlong(cur.c);
         const int cnt = uniform(cur.count);
