@@ -94,7 +94,10 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
         uint32_t nxd = (uint32_t)uniform((int)cur.next_depth);
         int next = (int)(nxd & kNextMask);
         // internal nodes, until the walk meets a leaf or leaves its range
-        while (next != k + 1) {
+        // (one exit test per pass; past the range the record read is the
+        // unused one after it)
+        bool inner = next != k + 1;
+        while (inner) {
             const int depth = (int)(nxd >> kNextBits);
             const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
@@ -102,6 +105,8 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             // (the compiler barrier keeps the load from sinking to its use), the
             // first child's only when the walk descends
             const NodeRec<T> over = nodes[(uint32_t)next];
+            NodeRec<T> first_child;
+            if (!EMIT) first_child = nodes[(uint32_t)(k + 1)];
             asm volatile("" ::: "memory");
             if (STATS) c.step += 1;
             // the test costs the same for every lane (some lane of the wave
@@ -128,16 +133,16 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 const bool here = lane == depth + 1;
                 mlo = here ? (int)(uint32_t)rej : mlo;
                 mhi = here ? (int)(uint32_t)(rej >> 32) : mhi;
-                nrec = nodes[(uint32_t)(k + 1)];
+                nrec = !EMIT ? first_child : nodes[(uint32_t)(k + 1)];
                 k = k + 1;
             } else {
                 k = next;
                 nrec = over;
             }
-            if (k >= kend) break;
             cur = nrec;
             nxd = (uint32_t)uniform((int)cur.next_depth);
             next = (int)(nxd & kNextMask);
+            inner = (k < kend) & (next != k + 1);
         }
         if (k >= kend) break;
         // leaf: exact terms with each of its points, skipping the query
