@@ -295,6 +295,8 @@ def main():
     ap.add_argument("--native-start-iteration", type=int, default=0,
                     help="with --write-native-input: run this many iterations on the GPU first and "
                          "write the embedding reached (the native run continues the schedule there)")
+    ap.add_argument("--item-points", type=int, default=None,
+                    help="Barnes-Hut work-item size S (library default 256)")
     ap.add_argument("--item-list", type=int, default=None,
                     help="item-list entries per phase-A wave (library default 256)")
     ap.add_argument("--hsne-lambda", type=float, default=None,
@@ -353,6 +355,8 @@ def main():
     ctx = hts.Context(0)
     if args.item_list is not None:
         ctx.set_item_list(args.item_list)
+    if args.item_points is not None:
+        ctx.set_item_points(args.item_points)
     Xd = torch.from_numpy(X).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -519,7 +523,8 @@ def main():
                                                             args.warmup + args.steps - 1),
                    "n": n, "d": d, "theta": args.theta, "perplexity": 30, "k": 90, "nnz": nnz,
                    "split_rule": "equal lengths, eq. (10)" if args.split_rule == 0
-                   else "equal areas, eq. (9)", "hsne_lambda": hs, "item_list": ctx.item_list},
+                   else "equal areas, eq. (9)", "hsne_lambda": hs, "item_list": ctx.item_list,
+                   "item_points": ctx.item_points},
         "exact_iters_per_s": round(exact_ips, 3) if exact_ips else None,
         "speedup_vs_exact": round(value / exact_ips, 1) if exact_ips else None,
         "kernel_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kt.items() if v[1]},
