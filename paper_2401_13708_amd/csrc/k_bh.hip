@@ -12,8 +12,9 @@
 // in two VGPRs used as lane-indexed arrays (readlane with the depth to read,
 // a lane select to write), and a mask serves directly as the lane predicate
 // of the masked term.  Node records are read with scalar loads; the next
-// sibling's is in flight while a node is evaluated, the first child's is
-// loaded when the walk descends, and enough waves per SIMD hide the latency.
+// sibling's is in flight while a node is evaluated, and so is the first
+// child's in the walks of the work items (phase A loads it when it descends);
+// enough waves per SIMD hide most of the latency.
 //
 // One wave walking the whole tree for its block is a long serial chain, so the
 // walk is split in two phases:
@@ -102,8 +103,9 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
             // the next sibling's record is loaded before the test and the term
-            // (the compiler barrier keeps the load from sinking to its use), the
-            // first child's only when the walk descends
+            // (the compiler barrier keeps the load from sinking to its use);
+            // the first child's too in the walks that emit no items, and only
+            // on descent in those that do (phase A)
             const NodeRec<T> over = nodes[(uint32_t)next];
             NodeRec<T> first_child;
             if (!EMIT) first_child = nodes[(uint32_t)(k + 1)];
