@@ -419,10 +419,13 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
     }
 }
 
-// Combine, stage 1: one wave per query block adds, slot by slot, the slot's
-// phase-A partial and then its items' partials in item order (eight loads in
-// flight at a time), then applies the query's common factor of the terms;
-// the counters of the block are added to the caller's totals.
+// Combine, stage 1: one workgroup per query block, one wave per phase-A slot.
+// Wave s adds its slot's phase-A partial and then its items' partials in item
+// order (eight loads in flight at a time); the first wave then adds the four
+// slot sums in slot order and applies the query's common factor of the terms.
+// The order of every sum is fixed, so the result does not depend on
+// scheduling.  The counters of the block are added to the caller's totals.
+static_assert(kTopSlots == kBlock / kWave, "one wave per phase-A slot");
 template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_gather(
     const PointRec<T> *__restrict__ spts,
@@ -431,8 +434,11 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
     const int *__restrict__ nitems_in, Jobs jb, int64_t nqb, int64_t n, T *__restrict__ frep,
     double *__restrict__ zq, const uint32_t *__restrict__ stats_top,
     const uint32_t *__restrict__ stats_items, unsigned long long *__restrict__ stats) {
-    const int64_t qb = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (qb >= nqb) return;
+    __shared__ T s_f[kTopSlots][2][kWave];
+    __shared__ double s_z[kTopSlots];
+    const int64_t qb = blockIdx.x;
+    if (qb >= nqb) return;  // the whole workgroup
+    const int sl = (int)(threadIdx.x / kWave);
     const int lane = (int)(threadIdx.x & (kWave - 1));
     int64_t q0;
     int cnt, job;
@@ -440,59 +446,50 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
     const int64_t q = q0 + lane;
     const bool valid = lane < cnt;
     T fx = 0, fy = 0;
-    double zb = 0.0;
-    unsigned long long s_all[kStats], s_it[kStats];
-#pragma unroll
-    for (int a = 0; a < kStats; ++a) s_all[a] = s_it[a] = 0;
-    for (int sl = 0; sl < kTopSlots; ++sl) {
-        const int64_t g = qb * kTopSlots + sl;
-        const int64_t b0 = uniform(item_base[g]);
-        const int ni = uniform(nitems_in[g]);
-        if (valid) {
-            fx += part0[((int64_t)sl * n + q) * 2];
-            fy += part0[((int64_t)sl * n + q) * 2 + 1];
-            constexpr int U = 8;
-            int j = 0;
-            for (; j + U <= ni; j += U) {
-                T px[U], py[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const T *p = part + ((b0 + j + u) * kWave + lane) * 2;
-                    px[u] = p[0];
-                    py[u] = p[1];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    fx += px[u];
-                    fy += py[u];
-                }
-            }
-            for (; j < ni; ++j) {
-                const T *p = part + ((b0 + j) * kWave + lane) * 2;
-                fx += p[0];
-                fy += p[1];
-            }
-        }
-        double zl = 0.0;
-        for (int j = lane; j < ni; j += kWave) zl += zitem[b0 + j];
-        zb += ztop[g] + wave_sum(zl);
-        if (STATS) {
-            for (int j = lane; j < ni; j += kWave)
-#pragma unroll
-                for (int a = 0; a < kStats; ++a) s_it[a] += stats_items[(b0 + j) * kStats + a];
-            if (lane == 0)
-#pragma unroll
-                for (int a = 0; a < kStats; ++a) s_all[a] += stats_top[g * kStats + a];
-        }
-    }
+    const int64_t g = qb * kTopSlots + sl;
+    const int64_t b0 = uniform(item_base[g]);
+    const int ni = uniform(nitems_in[g]);
     if (valid) {
-        // the query's common factor of the repulsive terms, once
-        const T f = Geo<MET>::qfactor(spts[q]);
-        frep[2 * q] = fx * f;
-        frep[2 * q + 1] = fy * f;
+        fx = part0[((int64_t)sl * n + q) * 2];
+        fy = part0[((int64_t)sl * n + q) * 2 + 1];
+        constexpr int U = 8;
+        int j = 0;
+        for (; j + U <= ni; j += U) {
+            T px[U], py[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const T *p = part + ((b0 + j + u) * kWave + lane) * 2;
+                px[u] = p[0];
+                py[u] = p[1];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                fx += px[u];
+                fy += py[u];
+            }
+        }
+        for (; j < ni; ++j) {
+            const T *p = part + ((b0 + j) * kWave + lane) * 2;
+            fx += p[0];
+            fy += p[1];
+        }
     }
-    if (lane == 0) zq[qb] = zb;
+    double zl = 0.0;
+    for (int j = lane; j < ni; j += kWave) zl += zitem[b0 + j];
+    const double zs = ztop[g] + wave_sum(zl);
+    s_f[sl][0][lane] = fx;
+    s_f[sl][1][lane] = fy;
+    if (lane == 0) s_z[sl] = zs;
     if (STATS) {
+        unsigned long long s_it[kStats], s_all[kStats];
+#pragma unroll
+        for (int a = 0; a < kStats; ++a) s_it[a] = s_all[a] = 0;
+        for (int j = lane; j < ni; j += kWave)
+#pragma unroll
+            for (int a = 0; a < kStats; ++a) s_it[a] += stats_items[(b0 + j) * kStats + a];
+        if (lane == 0)
+#pragma unroll
+            for (int a = 0; a < kStats; ++a) s_all[a] = stats_top[g * kStats + a];
 #pragma unroll
         for (int a = 0; a < kStats; ++a) {
             unsigned long long v = s_it[a], w = s_all[a];
@@ -507,6 +504,24 @@ __global__ __launch_bounds__(kBlock) void k_bh_gather(
             }
         }
     }
+    __syncthreads();
+    if (sl != 0) return;
+    double zb = s_z[0];
+#pragma unroll
+    for (int a = 1; a < kTopSlots; ++a) zb += s_z[a];
+    if (valid) {
+        T sx = s_f[0][0][lane], sy = s_f[0][1][lane];
+#pragma unroll
+        for (int a = 1; a < kTopSlots; ++a) {
+            sx += s_f[a][0][lane];
+            sy += s_f[a][1][lane];
+        }
+        // the query's common factor of the repulsive terms, once
+        const T f = Geo<MET>::qfactor(spts[q]);
+        frep[2 * q] = sx * f;
+        frep[2 * q + 1] = sy * f;
+    }
+    if (lane == 0) zq[qb] = zb;
 }
 
 // Combine, stage 2: g_i = 4 (a F_attr,i - F_rep,i / Z) scattered to input
@@ -610,7 +625,7 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
 
     const NodeRec<T> *nodes = (const NodeRec<T> *)(MET == 0 ? t->nodes : t->enodes);
     const PointRec<T> *spts = (const PointRec<T> *)t->spts;
-    const dim3 gq(cdiv(nqb, kBlock / kWave));
+    const dim3 gq(nqb);  // the combine: one workgroup per query block
     int64_t gi = cdiv(slots, kBlock / kWave);
     if (gi > 16384) gi = 16384;  // several waves per SIMD slot: the hardware balances the load
     if (gi < 1) gi = 1;          // an empty list (no items can be handed over)
