@@ -371,7 +371,8 @@ def main():
     hs = args.hsne_lambda
     if hs is not None and hs < 0:
         raise SystemExit("bench.py: --hsne-lambda must be >= 0")
-    nst = 10 if hs is None else 20
+    K = hts.STATS_BLOCK
+    nst = 2 * K if hs is None else 4 * K
 
     def run_pass(events, stats):
         """Warm-up + the timed iterations from the same start; the iteration
@@ -463,12 +464,12 @@ def main():
         avg_s = kms[dom] / launches[dom] / 1000.0
         if dom in ("traverse", "items"):
             def part(c):  # the kernel's share of one traversal's counters
-                return c[5:10] if dom == "items" else [a - b for a, b in zip(c[:5], c[5:10])]
+                return c[K:2 * K] if dom == "items" else [a - b for a, b in zip(c[:K], c[K:2 * K])]
             if hs is None:
-                share = part(st[:10])
+                share = part(st[:2 * K])
                 flops = (share[0] * F_TEST + (share[1] + share[2]) * F_PAIR) / launches[dom]
             else:  # two launches per iteration: the Euclidean walk, then the hyperbolic one
-                se, sh = part(st[:10]), part(st[10:20])
+                se, sh = part(st[:2 * K]), part(st[2 * K:4 * K])
                 flops = (se[0] * F_TEST_E + (se[1] + se[2]) * F_PAIR_E + sh[0] * F_TEST
                          + (sh[1] + sh[2]) * F_PAIR) / launches[dom]
             ach = flops / avg_s / 1e12
@@ -500,7 +501,8 @@ def main():
                 "leaf_pairs": c[2] // max(1, args.steps),
                 "wave_node_visits": c[3] // max(1, args.steps),
                 "wave_visits_with_work": c[4] // max(1, args.steps),
-                "share_of_item_walks": [round(b / a, 3) if a else 0.0 for a, b in zip(c[:5], c[5:10])]}
+                "points_covered": c[5] // max(1, args.steps),
+                "share_of_item_walks": [round(b / a, 3) if a else 0.0 for a, b in zip(c[:K], c[K:2 * K])]}
 
     workload = ("hyperbolic t-SNE Barnes-Hut iteration" if hs is None else
                 "h-SNE Barnes-Hut iteration (Euclidean term + %g x hyperbolic term)" % hs)
@@ -528,8 +530,8 @@ def main():
         "exact_iters_per_s": round(exact_ips, 3) if exact_ips else None,
         "speedup_vs_exact": round(value / exact_ips, 1) if exact_ips else None,
         "kernel_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kt.items() if v[1]},
-        "bh_counts_per_step": counts(st[:10]) if hs is None else
-        {"euclidean": counts(st[:10]), "hyperbolic": counts(st[10:20])},
+        "bh_counts_per_step": counts(st[:2 * K]) if hs is None else
+        {"euclidean": counts(st[:2 * K]), "hyperbolic": counts(st[2 * K:4 * K])},
         "setup_s": {"generate": round(gen_s, 2), "affinities_gpu": round(aff_s, 3)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -115,6 +115,8 @@ hts_status hts_tree_destroy(hts_tree tree);
  * by side (one tree per job, built, traversed and stepped in the same
  * launches).  Job j owns the n_per_job[j] >= 2 consecutive points after
  * those of jobs 0..j-1 of the concatenated Y; the sum must not exceed n_max.
+ * The job index is kept above the 2 max_depth cell bits of a 64-bit sort
+ * key, so ceil(log2(n_jobs)) + 2 max_depth must not exceed 64 (HTS_EINVAL).
  * n_per_job is a host array.  A new tree holds one job of whatever n the
  * next build is given; after this call every build must be given exactly
  * the layout's total.  Jobs in one layout see only their own points: their
@@ -159,19 +161,27 @@ hts_status hts_tree_export(hts_ctx ctx, hts_stream stream, hts_tree tree,
  * Z from float partial sums (one per subtree walk) added up in double.
  * ---------------------------------------------------------------------- */
 
-/* Exact O(n^2) repulsion. */
+/* Exact O(n^2) repulsion.  kl_dev: NULL, or a device double that receives
+ * the cost of eq. (3) with q_ij = w_ij / Z (eq. (12)), summed over the
+ * non-zeros of P:  sum_ij a p_ij (ln(a p_ij) - ln w_ij) + ln Z,  which is
+ * KL(P || Q) for a = 1 (sum P = 1) and in general the objective whose
+ * gradient grad holds.  Its terms are formed and summed in double (from the
+ * stored coordinates) in a fixed order. */
 hts_status hts_gradient_exact(hts_ctx ctx, hts_stream stream, const void *Y,
                               int64_t n, int32_t dtype, const int64_t *row_ptr,
                               const int32_t *col_idx, const void *p_val,
-                              double exaggeration, void *grad, double *z_dev);
+                              double exaggeration, void *grad, double *z_dev,
+                              double *kl_dev);
 
 /* Barnes-Hut repulsion (eq. (19)): a cell whose diameter r_cell and midpoint
  * m satisfy r_cell / d(y_i, m) < theta stands for its N_cell points;
  * theta = 0 evaluates every pair.  tree must have been built from the same Y.
- * stats_dev: NULL or device uint64[10] to which the call ADDS, in [0..4],
+ * stats_dev: NULL or device uint64[12] to which the call ADDS, in [0..5],
  * the number of node tests, accepted cells and exact leaf pairs (per query),
- * then the node visits and the visits with at least one interaction (per
- * wave); [5..9] receive the same five counts restricted to the second
+ * the node visits and the visits with at least one interaction (per wave),
+ * and the points the queries accounted for (N_cell per accepted cell plus 1
+ * per leaf pair; each query meets every other point once, so one call adds
+ * n (n - 1)); [6..11] receive the same six counts restricted to the second
  * traversal kernel (the walks of the small subtrees), so the first kernel's
  * share is the difference. */
 hts_status hts_gradient_bh(hts_ctx ctx, hts_stream stream, const void *Y,
@@ -194,7 +204,7 @@ hts_status hts_gradient_bh_jobs(hts_ctx ctx, hts_stream stream, const void *Y,
                                 double theta, void *grad, double *z_dev,
                                 uint64_t *stats_dev);
 
-/* h-SNE variant (Sec. 3).  The printed h-SNE variation is read as the sum
+/* h-SNE variant (Sec. 4-C).  The printed h-SNE variation is read as the sum
  * of a Euclidean t-SNE gradient of the disk coordinates and lambda times the
  * hyperbolic gradient above (the printed minus sign of the second part and
  * its missing factor d taken as misprints): the gradient of
@@ -207,8 +217,8 @@ hts_status hts_gradient_bh_jobs(hts_ctx ctx, hts_stream stream, const void *Y,
  * between two corners of the cell (angular widths of pi or more read as pi).
  * tree: built from the same Y, one job.  lambda: finite, >= 0.
  * z_dev: device double[2], receives Z^E then Z^H.  stats_dev: NULL or device
- * uint64[20]: [0..9] the counters of hts_gradient_bh for the Euclidean
- * traversal, [10..19] for the hyperbolic one (added to).  The first call
+ * uint64[24]: [0..11] the counters of hts_gradient_bh for the Euclidean
+ * traversal, [12..23] for the hyperbolic one (added to).  The first call
  * allocates the tree's Euclidean node records (cap entries). */
 hts_status hts_gradient_hsne(hts_ctx ctx, hts_stream stream, const void *Y,
                              int64_t n, int32_t dtype, const int64_t *row_ptr,
@@ -217,7 +227,7 @@ hts_status hts_gradient_hsne(hts_ctx ctx, hts_stream stream, const void *Y,
                              double theta, void *grad, double *z_dev,
                              uint64_t *stats_dev);
 
-/* CO-SNE variant (Sec. 3): turns the KL gradient in grad (from either
+/* CO-SNE variant (Sec. 4-C): turns the KL gradient in grad (from either
  * gradient call, same Y) into the gradient of
  *   lambda1 KL(P||Q) + (lambda2 / n) sum_i (|x_i|^2 - |y_i|^2)^2,
  * in place: grad_i <- lambda1 grad_i - (4 lambda2 / n)(|x_i|^2 - |y_i|^2) y_i,
@@ -278,6 +288,14 @@ hts_status hts_set_item_points(hts_ctx ctx, int32_t item_points);
  * and run slower once waves exceed their share.  Default 256 (every walk a
  * wave records; larger values act as 256); applies to later calls on ctx. */
 hts_status hts_set_item_list(hts_ctx ctx, int32_t items_per_wave);
+
+/* Workspace generation of ctx (host, *gen_out).  The context keeps device
+ * workspaces that grow on demand, and a job layout (hts_tree_set_jobs)
+ * replaces its tree's tables; either reallocation changes this counter.
+ * Launches recorded into a HIP graph reference the device memory of the
+ * moment of capture: replaying such a graph is valid only while the counter
+ * keeps the value it had when the graph was captured (re-capture otherwise). */
+hts_status hts_workspace_generation(hts_ctx ctx, uint64_t *gen_out);
 
 /* ------------------------------------------------------------------------
  * Kernel timing with HIP events on the caller's stream (for benchmarks).

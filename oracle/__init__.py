@@ -304,14 +304,15 @@ def gradient_bh(Y, rp, col, val, tree: Tree, theta: float, exaggeration: float =
     rp, col, val = _csr(rp, col, val)
     g = np.zeros_like(Y)
     z = np.zeros(1)
-    cnt = np.zeros(3, dtype=np.int64)
+    cnt = np.zeros(4, dtype=np.int64)
     _check(lib().ora_gradient_bh(_p(Y, _D), Y.shape[0], _p(rp, _I64), _p(col, _I32), _p(val, _D),
                                  float(exaggeration), tree.h, float(theta), _p(g, _D), _p(z, _D),
                                  _p(cnt, _I64)), "gradient_bh")
-    return g, float(z[0]), dict(tests=int(cnt[0]), accepts=int(cnt[1]), pairs=int(cnt[2]))
+    return g, float(z[0]), dict(tests=int(cnt[0]), accepts=int(cnt[1]), pairs=int(cnt[2]),
+                                covered=int(cnt[3]))
 
 
-# ---- h-SNE (Sec. 3): Euclidean Student-t term of the disk coordinates ----
+# ---- h-SNE (Sec. 4-C): Euclidean Student-t term of the disk coordinates ----
 
 def euclid_cost(Y, rp, col, val, exaggeration: float = 1.0) -> float:
     """KL(P || Q^E) with q^E proportional to (1 + |y_i - y_j|^2)^-1."""
@@ -339,11 +340,12 @@ def gradient_euclid_bh(Y, rp, col, val, tree: Tree, theta: float, exaggeration: 
     rp, col, val = _csr(rp, col, val)
     g = np.zeros_like(Y)
     z = np.zeros(1)
-    cnt = np.zeros(3, dtype=np.int64)
+    cnt = np.zeros(4, dtype=np.int64)
     _check(lib().ora_gradient_euclid_bh(_p(Y, _D), Y.shape[0], _p(rp, _I64), _p(col, _I32),
                                         _p(val, _D), float(exaggeration), tree.h, float(theta),
                                         _p(g, _D), _p(z, _D), _p(cnt, _I64)), "gradient_euclid_bh")
-    return g, float(z[0]), dict(tests=int(cnt[0]), accepts=int(cnt[1]), pairs=int(cnt[2]))
+    return g, float(z[0]), dict(tests=int(cnt[0]), accepts=int(cnt[1]), pairs=int(cnt[2]),
+                                covered=int(cnt[3]))
 
 
 def hsne_cost(Y, rp, col, val, lam: float, exaggeration: float = 1.0) -> float:

@@ -349,7 +349,7 @@ int ora_kl_cost(const double *Y, int64_t n, const int64_t *row_ptr,
     return 0;
 }
 
-/* CO-SNE (Sec. 3): the cost lambda1 KL(P||Q) + (lambda2 / n) sum_i
+/* CO-SNE (Sec. 4-C): the cost lambda1 KL(P||Q) + (lambda2 / n) sum_i
  * (|x_i|^2 - |y_i|^2)^2, with xnorm2[i] = |x_i|^2 of the input point.
  * reading: the printed variation of the second part has the sign of
  * +(4 lambda2 / n)(|x_i|^2 - |y_i|^2) y_i; the derivative of the stated cost is
@@ -880,6 +880,7 @@ typedef struct {
     double yx, yy;
     double fx, fy, z;
     int64_t tests, accepts, pairs;
+    int64_t covered; /* points stood for: N_cell per accepted cell, 1 per leaf pair */
 } bh_state;
 
 /* Depth-first traversal (Sec. 4-B): at an internal node the condition
@@ -901,6 +902,7 @@ static void bh_visit(bh_state *s, int32_t nid) {
             s->fy += w * w * f[1];
             s->z += w;
             s->pairs++;
+            s->covered++;
         }
         return;
     }
@@ -917,6 +919,7 @@ static void bh_visit(bh_state *s, int32_t nid) {
         s->fy += nc * w * w * f[1];
         s->z += nc * w;
         s->accepts++;
+        s->covered += o->count;
         return;
     }
     for (int c = 0; c < 4; ++c)
@@ -932,7 +935,7 @@ int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
     int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
     double *fr = (double *)malloc(sizeof(double) * (size_t)(2 * n));
     double *zi = (double *)malloc(sizeof(double) * (size_t)n);
-    int64_t *cnt = (int64_t *)calloc((size_t)(3 * n), sizeof(int64_t));
+    int64_t *cnt = (int64_t *)calloc((size_t)(4 * n), sizeof(int64_t));
     if (!pos || !fr || !zi || !cnt) { free(pos); free(fr); free(zi); free(cnt); return -2; }
     for (int64_t k = 0; k < m; ++k) pos[t->pre[k]] = k;
 #pragma omp parallel for num_threads(NTH()) schedule(dynamic, 64)
@@ -949,9 +952,10 @@ int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
         fr[2 * i] = s.fx;
         fr[2 * i + 1] = s.fy;
         zi[i] = s.z;
-        cnt[3 * i] = s.tests;
-        cnt[3 * i + 1] = s.accepts;
-        cnt[3 * i + 2] = s.pairs;
+        cnt[4 * i] = s.tests;
+        cnt[4 * i + 1] = s.accepts;
+        cnt[4 * i + 2] = s.pairs;
+        cnt[4 * i + 3] = s.covered;
     }
     double z = 0.0;
     for (int64_t i = 0; i < n; ++i) z += zi[i];
@@ -964,11 +968,12 @@ int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
     }
     if (z_out) *z_out = z;
     if (counters) {
-        counters[0] = counters[1] = counters[2] = 0;
+        counters[0] = counters[1] = counters[2] = counters[3] = 0;
         for (int64_t i = 0; i < n; ++i) {
-            counters[0] += cnt[3 * i];
-            counters[1] += cnt[3 * i + 1];
-            counters[2] += cnt[3 * i + 2];
+            counters[0] += cnt[4 * i];
+            counters[1] += cnt[4 * i + 1];
+            counters[2] += cnt[4 * i + 2];
+            counters[3] += cnt[4 * i + 3];
         }
     }
     free(pos); free(fr); free(zi); free(cnt);
@@ -976,7 +981,7 @@ int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
 }
 
 /* ======================================================================
- * h-SNE (Sec. 3): a Euclidean Student-t term on the disk coordinates
+ * h-SNE (Sec. 4-C): a Euclidean Student-t term on the disk coordinates
  * ======================================================================
  * reading: the printed h-SNE variation is the sum of a Euclidean t-SNE
  * gradient of the disk coordinates (the form of eq. (4)) and lambda times the
@@ -1082,6 +1087,7 @@ static void bh_visit_euclid(bh_state *s, int32_t nid) {
             s->fy += w * w * dy;
             s->z += w;
             s->pairs++;
+            s->covered++;
         }
         return;
     }
@@ -1097,6 +1103,7 @@ static void bh_visit_euclid(bh_state *s, int32_t nid) {
         s->fy += nc * w * w * dy;
         s->z += nc * w;
         s->accepts++;
+        s->covered += o->count;
         return;
     }
     for (int ch = 0; ch < 4; ++ch)
@@ -1112,7 +1119,7 @@ int ora_gradient_euclid_bh(const double *Y, int64_t n, const int64_t *row_ptr,
     int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
     double *fr = (double *)malloc(sizeof(double) * (size_t)(2 * n));
     double *zi = (double *)malloc(sizeof(double) * (size_t)n);
-    int64_t *cnt = (int64_t *)calloc((size_t)(3 * n), sizeof(int64_t));
+    int64_t *cnt = (int64_t *)calloc((size_t)(4 * n), sizeof(int64_t));
     if (!pos || !fr || !zi || !cnt) { free(pos); free(fr); free(zi); free(cnt); return -2; }
     for (int64_t k = 0; k < m; ++k) pos[t->pre[k]] = k;
 #pragma omp parallel for num_threads(NTH()) schedule(dynamic, 64)
@@ -1129,9 +1136,10 @@ int ora_gradient_euclid_bh(const double *Y, int64_t n, const int64_t *row_ptr,
         fr[2 * i] = s.fx;
         fr[2 * i + 1] = s.fy;
         zi[i] = s.z;
-        cnt[3 * i] = s.tests;
-        cnt[3 * i + 1] = s.accepts;
-        cnt[3 * i + 2] = s.pairs;
+        cnt[4 * i] = s.tests;
+        cnt[4 * i + 1] = s.accepts;
+        cnt[4 * i + 2] = s.pairs;
+        cnt[4 * i + 3] = s.covered;
     }
     double z = 0.0;
     for (int64_t i = 0; i < n; ++i) z += zi[i];
@@ -1143,11 +1151,12 @@ int ora_gradient_euclid_bh(const double *Y, int64_t n, const int64_t *row_ptr,
     }
     if (z_out) *z_out = z;
     if (counters) {
-        counters[0] = counters[1] = counters[2] = 0;
+        counters[0] = counters[1] = counters[2] = counters[3] = 0;
         for (int64_t i = 0; i < n; ++i) {
-            counters[0] += cnt[3 * i];
-            counters[1] += cnt[3 * i + 1];
-            counters[2] += cnt[3 * i + 2];
+            counters[0] += cnt[4 * i];
+            counters[1] += cnt[4 * i + 1];
+            counters[2] += cnt[4 * i + 2];
+            counters[3] += cnt[4 * i + 3];
         }
     }
     free(pos); free(fr); free(zi); free(cnt);

@@ -46,7 +46,7 @@ int ora_build_affinities(const double *X, int64_t n, int32_t d, double perplexit
 int ora_kl_cost(const double *Y, int64_t n, const int64_t *row_ptr,
                 const int32_t *col, const double *val, double exaggeration,
                 double *cost_out);
-/* CO-SNE (Sec. 3): cost lambda1 KL + (lambda2/n) sum (|x_i|^2 - |y_i|^2)^2 and
+/* CO-SNE (Sec. 4-C): cost lambda1 KL + (lambda2/n) sum (|x_i|^2 - |y_i|^2)^2 and
  * its gradient from a KL gradient g_kl */
 int ora_cosne_cost(const double *Y, int64_t n, const int64_t *row_ptr, const int32_t *col,
                    const double *val, const double *xnorm2, double lambda1, double lambda2,
@@ -88,9 +88,13 @@ int ora_tree_export(const ora_tree *t, int32_t *count, int32_t *depth,
 int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
                     const int32_t *col, const double *val, double exaggeration,
                     const ora_tree *t, double theta, double *grad,
-                    double *z_out, int64_t *counters /* tests, accepts, leaf pairs; or NULL */);
+                    double *z_out, int64_t *counters);
+/* counters: NULL or int64[4] receiving, summed over the queries, the node
+ * tests, the accepted cells, the exact leaf pairs and the points the query
+ * accounted for (N_cell per accepted cell plus 1 per leaf pair); every query
+ * meets each other point exactly once, so the last one equals n (n - 1). */
 
-/* ---- h-SNE (Sec. 3): the Euclidean Student-t term of the disk coordinates ----
+/* ---- h-SNE (Sec. 4-C): the Euclidean Student-t term of the disk coordinates ----
  * cost KL(P || Q^E) with q^E_ij proportional to (1 + |y_i - y_j|^2)^-1; its
  * exact gradient; and the same accelerated over the polar quadtree with
  * Euclidean centres of mass and the criterion ediam / |y_i - c| < theta.

@@ -92,6 +92,7 @@ class JobBatch:
         self.tree.set_jobs(sizes)
         self.iters_done = 0
         self.graph = None
+        self.graph_gen = -1
 
     def _launch(self, stats=None):
         s = self.sched
@@ -104,24 +105,34 @@ class JobBatch:
                       self.mu, s.min_gain, s.boundary_eps, s.metric_power)
 
     def iterate(self, stats=None):
-        if self.graph is not None and stats is None:
+        if self.graph is not None and stats is None and self.ctx.generation() == self.graph_gen:
             self.graph.replay()
         else:
             self._launch(stats)
+            if self.graph is not None and stats is None:
+                # a workspace the graph points into was reallocated since the
+                # capture (another call on the context needed more): record
+                # the iteration again against the current workspaces
+                self._record()
         self.iters_done += 1
+
+    def _record(self):
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._launch()
+        self.graph, self.graph_gen = g, self.ctx.generation()
 
     def capture(self):
         """Records one iteration of all jobs (schedule, tree, gradient, step:
         every kernel of it, no memory clears or allocations) as a HIP graph,
         which `iterate` then replays.  The iteration before the capture runs
         eagerly so that the library's workspaces exist; the per-job iteration
-        counters live on the device, so every replay is the next iteration."""
+        counters live on the device, so every replay is the next iteration.
+        A replay is skipped in favour of a new capture when the context's
+        workspaces were reallocated after the graph was recorded."""
         self.iterate()
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self._launch()
-        self.graph = g
+        self._record()
         return self
 
     def run(self, iters: int):

@@ -39,6 +39,7 @@ hts_status ensure(Buffer &b, size_t bytes) {
         b.bytes = 0;
     }
     size_t want = bytes < 256 ? 256 : bytes;
+    if (b.gen) ++*b.gen;  // pointers to the old allocation are stale from here on
     hipError_t e = hipMalloc(&b.p, want);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
     b.bytes = want;
@@ -91,6 +92,8 @@ hts_status hts_create(int32_t device, hts_ctx *out) {
     HTS_HIP(hipSetDevice(device));
     hts_ctx c = new hts_ctx_s();
     c->device = device;
+    for (Buffer *b : {&c->pts, &c->fattr, &c->frep, &c->zpart, &c->part, &c->spare}) b->gen = &c->gen;
+    for (Buffer &b : c->aff) b.gen = &c->gen;
     hipError_t e = hipMalloc(&c->d_err, 64);
     if (e != hipSuccess) {
         delete c;
@@ -272,6 +275,14 @@ hts_status hts_tree_set_jobs(hts_tree t, int32_t n_jobs, const int64_t *n_per_jo
     const int64_t nqb = jqb[n_jobs];
     if (nqb > cdiv(t->n_max, kWave) + n_jobs)
         return fail(HTS_EINVAL, "hts_tree_set_jobs: too many query blocks");
+    // the job index sits above the 2 max_depth cell bits of a 64-bit key
+    int bits = 0;
+    while ((1 << bits) < n_jobs) ++bits;
+    if (bits + 2 * t->max_depth > 64)
+        return fail(HTS_EINVAL,
+                    "hts_tree_set_jobs: %d jobs need %d key bits above the %d cell bits of "
+                    "max_depth %d; at most 64 in all",
+                    n_jobs, bits, 2 * t->max_depth, t->max_depth);
     std::vector<int32_t> pj((size_t)n), qj((size_t)nqb);
     for (int32_t j = 0; j < n_jobs; ++j) {
         for (int64_t i = off[j]; i < off[j + 1]; ++i) pj[(size_t)i] = j;
@@ -284,6 +295,7 @@ hts_status hts_tree_set_jobs(hts_tree t, int32_t n_jobs, const int64_t *n_per_jo
     const size_t bytes[] = {off.size() * 8, jqb.size() * 4,
                             (size_t)(nqb > cdiv(t->n_max, kWave) ? nqb : cdiv(t->n_max, kWave)) * 4,
                             (size_t)n_jobs * 16};
+    ++t->ctx->gen;  // the tables below move
     for (int a = 0; a < 4; ++a) {
         HTS_HIP(hipFree(*tabs[a]));
         *tabs[a] = nullptr;
@@ -298,8 +310,6 @@ hts_status hts_tree_set_jobs(hts_tree t, int32_t n_jobs, const int64_t *n_per_jo
     t->nqb = nqb;
     t->jobs_set = true;
     t->tab_n = n;
-    int bits = 0;
-    while ((1 << bits) < n_jobs) ++bits;
     t->job_bits = bits;
     t->n = 0;  // nothing built for this layout yet
     return HTS_OK;
@@ -405,33 +415,40 @@ static hts_status grad_args(const char *fn, hts_ctx c, const void *Y, int64_t n,
 }
 
 template <typename T>
-static hts_status exact_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, const int64_t *rp,
-                             const int32_t *col, const T *val, double ex, T *grad, double *z_dev) {
+static hts_status exact_ws_grow(hts_ctx c, int64_t n, bool kl, ExactWs &w) {
     HTS_OKR(ensure(c->pts, (size_t)n * sizeof(PointRec<T>)));
     HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
     HTS_OKR(ensure(c->frep, (size_t)n * 2 * sizeof(double)));
     HTS_OKR(ensure(c->zpart, (size_t)(cdiv(n, kBlock) + 8) * sizeof(double)));
-    PointRec<T> *pts = (PointRec<T> *)c->pts.p;
-    HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
-    HTS_OKR(launch_attract<T>(c, st, pts, rp, col, val, n, (T *)c->fattr.p));
-    int64_t nz = 0;
-    HTS_OKR(launch_exact<T>(c, st, pts, n, (double *)c->frep.p, (double *)c->zpart.p, &nz));
-    return launch_finalize<T, double>(c, st, (const T *)c->fattr.p, (const double *)c->frep.p,
-                                      (const double *)c->zpart.p, nz, n, ex, grad, z_dev);
+    HTS_OKR(ensure(c->part, exact_part_bytes(n)));
+    if (kl) HTS_OKR(ensure(c->spare, (size_t)kl_parts(n) * sizeof(double)));
+    w.pts = c->pts.p;
+    w.fattr = c->fattr.p;
+    w.frep = (double *)c->frep.p;
+    w.zpart = (double *)c->zpart.p;
+    w.part = (double *)c->part.p;
+    w.klpart = kl ? (double *)c->spare.p : nullptr;
+    return HTS_OK;
 }
 
 extern "C" hts_status hts_gradient_exact(hts_ctx c, hts_stream stream, const void *Y, int64_t n,
                               int32_t dtype, const int64_t *row_ptr, const int32_t *col_idx,
-                              const void *p_val, double exaggeration, void *grad, double *z_dev) {
+                              const void *p_val, double exaggeration, void *grad, double *z_dev,
+                              double *kl_dev) {
     HTS_OKR(grad_args("hts_gradient_exact", c, Y, n, dtype, row_ptr, col_idx, p_val, exaggeration,
                       grad, z_dev));
     HTS_HIP(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
-    if (dtype == HTS_F64)
+    ExactWs w;
+    if (dtype == HTS_F64) {
+        HTS_OKR(exact_ws_grow<double>(c, n, kl_dev != nullptr, w));
         return exact_impl<double>(c, st, (const double *)Y, n, row_ptr, col_idx,
-                                  (const double *)p_val, exaggeration, (double *)grad, z_dev);
+                                  (const double *)p_val, exaggeration, (double *)grad, z_dev,
+                                  kl_dev, w, true);
+    }
+    HTS_OKR(exact_ws_grow<float>(c, n, kl_dev != nullptr, w));
     return exact_impl<float>(c, st, (const float *)Y, n, row_ptr, col_idx, (const float *)p_val,
-                             exaggeration, (float *)grad, z_dev);
+                             exaggeration, (float *)grad, z_dev, kl_dev, w, true);
 }
 
 template <typename T>
@@ -534,7 +551,7 @@ static hts_status hsne_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, co
                                        val, fattr, ex, nullptr, false, 1.0, grad, z_dev, stats)));
     return launch_bh_repulsion<T, 0>(c, st, t, n, BhPrep<T>{Y, theta, false, true}, pts, rp, col,
                                      val, fattr, ex, nullptr, true, lambda, grad, z_dev + 1,
-                                     stats ? stats + 10 : nullptr);
+                                     stats ? stats + 2 * kBhStats : nullptr);
 }
 
 extern "C" {
@@ -673,6 +690,12 @@ hts_status hts_set_item_list(hts_ctx c, int32_t items_per_wave) {
     if (items_per_wave < 0)
         return fail(HTS_EINVAL, "hts_set_item_list: items_per_wave must be >= 0");
     c->list_items = items_per_wave;
+    return HTS_OK;
+}
+
+hts_status hts_workspace_generation(hts_ctx c, uint64_t *gen_out) {
+    if (!c || !gen_out) return fail(HTS_EINVAL, "hts_workspace_generation: NULL argument");
+    *gen_out = c->gen;
     return HTS_OK;
 }
 

@@ -46,6 +46,10 @@ template <> struct alignas(16) NodeRec<double> {
     double c;
     double pad;
 };
+// traversal counters per stats block of the Barnes-Hut calls: node tests,
+// accepted cells, exact leaf pairs, wave node visits, visits with at least one
+// interaction, points accounted for (N_cell per accepted cell, 1 per pair)
+constexpr int kBhStats = 6;
 constexpr int kNextBits = 26;
 constexpr uint32_t kNextMask = (1u << kNextBits) - 1u;
 constexpr int64_t kMaxNodes = (int64_t)1 << kNextBits;
@@ -83,6 +87,7 @@ struct Timing {
 struct Buffer {
     void *p = nullptr;
     size_t bytes = 0;
+    uint64_t *gen = nullptr;  // the owning context's generation, bumped on reallocation
 };
 
 }  // namespace hts
@@ -92,6 +97,9 @@ struct hts_ctx_s {
     int32_t item_points = 256;  // Barnes-Hut work-item size S (hts_set_item_points)
     int32_t list_items = 256;   // item-list entries per phase-A wave (hts_set_item_list)
     uint32_t *d_err = nullptr;
+    // changes whenever device memory that launches on this context referenced
+    // is reallocated (a workspace grown, a job layout's tables replaced)
+    uint64_t gen = 0;
     hts::Buffer pts, fattr, frep, zpart, part, spare;
     hts::Buffer aff[8];
     hts::Timing timing;
@@ -198,9 +206,11 @@ hts_status radix_sort_pairs(hipStream_t st, uint64_t *keys_io, uint32_t *vals_io
                             uint64_t *keys_out, uint32_t *vals_out, int64_t n, int bits,
                             void *tmp);
 
+// timed: bracket the launch with the context's timing events (when on)
 template <typename T>
 hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, const int64_t *rp,
-                          const int32_t *col, const T *val, int64_t n, T *fattr);
+                          const int32_t *col, const T *val, int64_t n, T *fattr,
+                          bool timed = true);
 
 // What the launch that starts a traversal also does: the point records of Y
 // into pts (points) and the criterion thresholds of the tree's hyperbolic
@@ -226,14 +236,46 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
                                const double *ex_job, bool accumulate, double scale, T *grad,
                                double *z_dev, uint64_t *stats);
 
+// the exact repulsion's per-chunk partials: exact_part_bytes(n) bytes in part
+size_t exact_part_bytes(int64_t n);
 template <typename T>
 hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,
-                        double *frep, double *zpart, int64_t *nz_out);
+                        double *part, double *frep, double *zpart, int64_t *nz_out,
+                        bool timed = true);
 
 template <typename T, typename FR>
 hts_status launch_finalize(hts_ctx ctx, hipStream_t st, const T *fattr, const FR *frep,
                            const double *zpart, int64_t nz, int64_t n, double ex, T *grad,
-                           double *z_dev);
+                           double *z_dev, bool timed = true);
+
+// Device memory of one exact-gradient call: point records, attractive
+// forces, repulsive forces, Z partials, the repulsion's chunk partials and the
+// cost's block sums (klpart may be NULL when no cost is asked for).
+struct ExactWs {
+    void *pts;
+    void *fattr;
+    double *frep, *zpart, *part, *klpart;
+};
+// bytes of those pieces for n points (sizes[6], each rounded up to 256) and
+// their total; exact_carve lays them out one after another from base
+template <typename T>
+size_t exact_ws_bytes(int64_t n, size_t sizes[6]);
+template <typename T>
+ExactWs exact_carve(char *base, int64_t n);
+// the exact gradient (and the cost when kl_dev is not NULL) on workspace w;
+// timed: the launches carry the context's timing events when timing is on
+template <typename T>
+hts_status exact_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, const int64_t *rp,
+                      const int32_t *col, const T *val, double ex, T *grad, double *z_dev,
+                      double *kl_dev, const ExactWs &w, bool timed);
+
+// the cost of eq. (3) into *kl_dev (after *z_dev holds Z); part holds
+// kl_parts(n) doubles
+int64_t kl_parts(int64_t n);
+template <typename T>
+hts_status launch_kl(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, const int64_t *rp,
+                     const int32_t *col, const T *val, int64_t n, double ex, double *part,
+                     const double *z_dev, double *kl_dev);
 
 template <typename T>
 hts_status launch_cosne(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, const double *xnorm2,

@@ -119,7 +119,7 @@ __device__ __forceinline__ PairTerm<float> pair_term<float, false>(float qx, flo
 // The traversal and the attractive rows are written once over a metric:
 //  Geo<0>: the Poincare disk (eqs. (8), (13)), terms w^m d dd/dy as above;
 //  Geo<1>: the Euclidean Student-t kernel of the disk coordinates (the first
-//          part of the h-SNE gradient, Sec. 3): w = (1 + |y - o|^2)^-1, terms
+//          part of the h-SNE gradient, Sec. 4-C): w = (1 + |y - o|^2)^-1, terms
 //          w^m (y - o); the criterion argument is |y - o|^2 itself.
 // arg() returns the quantity compared with a node's threshold; attract() and
 // repel() add p w (...) and N w^2 (...) to the force and N w to Z, except

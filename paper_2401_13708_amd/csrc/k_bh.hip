@@ -33,14 +33,14 @@
 //
 // The walk is written once over a metric (Geo<MET>): the Poincare disk for
 // the hyperbolic gradient, and the Euclidean Student-t kernel of the disk
-// coordinates for the first part of the h-SNE gradient (Sec. 3), which walks
+// coordinates for the first part of the h-SNE gradient (Sec. 4-C), which walks
 // the same tree with Euclidean node records.
 #include "hts_impl.hpp"
 #include "hts_math.hpp"
 
 namespace hts {
 
-constexpr int kStats = 5;
+constexpr int kStats = kBhStats;
 constexpr int kAttractLanes = 16;  // lanes per CSR row of the attractive term
 constexpr int kItemCap = 256;  // items one phase-A wave can hand to phase B
 // The item list holds ctx->list_items items per phase-A wave (kItemCap by
@@ -66,7 +66,7 @@ struct alignas(16) ItemRec {
 };
 
 struct Counters {
-    unsigned long long test = 0, acc = 0, pair = 0, step = 0, work = 0;
+    unsigned long long test = 0, acc = 0, pair = 0, step = 0, work = 0, cover = 0;
 };
 
 // Depth-first walk of the pre-order range [k, kend), which starts at a node
@@ -125,6 +125,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 c.test += __popcll(m);
                 c.acc += __popcll(am);
                 c.work += am != 0;
+                c.cover += (unsigned long long)__popcll(am) * (unsigned)cur.count;
             }
             if (EMIT && rej && cur.count <= S && nitems < kItemCap) {
                 if (lane == 0) items[nitems] = LdsItem{k, nxd, rej};
@@ -166,6 +167,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             if (STATS) {
                 const uint64_t um = __ballot(use);
                 c.pair += __popcll(um);
+                c.cover += __popcll(um);
                 c.work += um != 0;
             }
         } else {
@@ -177,7 +179,11 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                     double t = Geo<MET>::arg(me, o.x, o.y, o.ia, dd);
                     Geo<MET>::repel(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, zw);
                 }
-                if (STATS) c.pair += __popcll(__ballot(use));
+                if (STATS) {
+                    const int u = __popcll(__ballot(use));
+                    c.pair += u;
+                    c.cover += u;
+                }
             }
         }
         k = next;
@@ -194,6 +200,7 @@ __device__ __forceinline__ void put_stats(uint32_t *__restrict__ sp, const Count
     sp[2] = (uint32_t)c.pair;
     sp[3] = (uint32_t)c.step;
     sp[4] = (uint32_t)c.work;
+    sp[5] = (uint32_t)c.cover;
 }
 
 // Phase A: the walk of a query block over the nodes of more than S points,
@@ -275,6 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_top(
             c.acc += __popcll(am);
             c.step += 1;
             c.work += am != 0;
+            c.cover += (unsigned long long)__popcll(am) * (unsigned)A.count;
         }
         if (rej && A.count <= S) {  // the rejecting lanes take the cell as one work item
             if (owner) {

@@ -39,9 +39,9 @@ __global__ __launch_bounds__(kBlock) void k_attract(const PointRec<T> *__restric
 
 template <typename T>
 hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, const int64_t *rp,
-                          const int32_t *col, const T *val, int64_t n, T *fattr) {
+                          const int32_t *col, const T *val, int64_t n, T *fattr, bool timed) {
     constexpr int G = 16;
-    TimedScope ts(ctx, st, HTS_K_ATTRACT);
+    TimedScope ts(timed ? ctx : nullptr, st, HTS_K_ATTRACT);
     hipLaunchKernelGGL((k_attract<T, G>), dim3(cdiv(n * G, kBlock)), dim3(kBlock), 0, st, pts, rp,
                        col, val, n, fattr, ctx->d_err);
     HTS_HIP(hipGetLastError());
@@ -117,21 +117,31 @@ __global__ __launch_bounds__(kBlock) void k_exact_reduce(const double *__restric
     if (threadIdx.x == 0) zpart[blockIdx.x] = sh[0];
 }
 
-template <typename T>
-hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,
-                        double *frep, double *zpart, int64_t *nz_out) {
-    int64_t qblocks = cdiv(n, kBlock);
-    // about 8 waves per SIMD on 256 CUs x 4 SIMDs
-    int64_t nchunks = cdiv(8192, qblocks * (kBlock / kWave));
+// chunks of j per query block: about 8 waves per SIMD on 256 CUs x 4 SIMDs
+static void exact_chunks(int64_t n, int64_t &nchunks, int64_t &chunk_len) {
+    const int64_t qblocks = cdiv(n, kBlock);
+    nchunks = cdiv(8192, qblocks * (kBlock / kWave));
     if (nchunks < 1) nchunks = 1;
     if (nchunks > 64) nchunks = 64;
     if (nchunks > n) nchunks = n;
-    int64_t chunk_len = cdiv(n, nchunks);
+    chunk_len = cdiv(n, nchunks);
     nchunks = cdiv(n, chunk_len);
-    HTS_OKR(ensure(ctx->part, (size_t)(nchunks * n * 3) * sizeof(double)));
-    double *part = (double *)ctx->part.p;
+}
+
+size_t exact_part_bytes(int64_t n) {
+    int64_t nchunks, chunk_len;
+    exact_chunks(n, nchunks, chunk_len);
+    return (size_t)(nchunks * n * 3) * sizeof(double);
+}
+
+template <typename T>
+hts_status launch_exact(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, int64_t n,
+                        double *part, double *frep, double *zpart, int64_t *nz_out, bool timed) {
+    const int64_t qblocks = cdiv(n, kBlock);
+    int64_t nchunks, chunk_len;
+    exact_chunks(n, nchunks, chunk_len);
     {
-        TimedScope ts(ctx, st, HTS_K_EXACT);
+        TimedScope ts(timed ? ctx : nullptr, st, HTS_K_EXACT);
         hipLaunchKernelGGL(k_exact<T>, dim3(qblocks, nchunks), dim3(kBlock), 0, st, pts, n,
                            chunk_len, part);
         HTS_HIP(hipGetLastError());
@@ -179,11 +189,142 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const T *__restrict__ fattr
 template <typename T, typename FR>
 hts_status launch_finalize(hts_ctx ctx, hipStream_t st, const T *fattr, const FR *frep,
                            const double *zpart, int64_t nz, int64_t n, double ex, T *grad,
-                           double *z_dev) {
-    TimedScope ts(ctx, st, HTS_K_FINALIZE);
+                           double *z_dev, bool timed) {
+    TimedScope ts(timed ? ctx : nullptr, st, HTS_K_FINALIZE);
     hipLaunchKernelGGL((k_finalize<T, FR>), dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, fattr, frep,
                        zpart, nz, n, ex, grad, z_dev, ctx->d_err);
     HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
+// ---------------------------------------------------------------- cost
+// The cost of eq. (3) with q_ij = w_ij / Z (eq. (12)), evaluated over the
+// non-zeros of P:  C = sum_ij a p_ij (ln(a p_ij) - ln w_ij) + ln Z, which for
+// exaggeration a = 1 is KL(P || Q) (sum P = 1) and in general the objective
+// whose gradient the gradient calls return.  Every term is formed in double
+// from the stored coordinates (ln w = -ln(1 + d^2), d from the double
+// distance argument); 16 lanes share a row, their sums are combined in a
+// fixed butterfly and the rows of a workgroup in row order, so the result is
+// the same from run to run.
+constexpr int kKlLanes = 16;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kl_rows(const PointRec<T> *__restrict__ pts,
+                                                    const int64_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ col,
+                                                    const T *__restrict__ val, int64_t n, double ex,
+                                                    double *__restrict__ part,
+                                                    uint32_t *__restrict__ err) {
+    __shared__ double s_row[kBlock / kKlLanes];
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t row = gid / kKlLanes;
+    const int sub = (int)(gid % kKlLanes);
+    double c = 0.0;
+    if (row < n) {
+        const PointRec<T> q = pts[row];
+        for (int64_t e = rp[row] + sub; e < rp[row + 1]; e += kKlLanes) {
+            const int32_t j = col[e];
+            if ((uint32_t)j >= (uint64_t)n) {
+                atomicOr(err, HTS_ERR_BAD_INDEX);
+                continue;
+            }
+            const double p = ex * (double)val[e];
+            if (!(p > 0.0)) continue;
+            const PointRec<T> o = pts[j];
+            double dq, sh;
+            const double t = dist_arg<T>(q.x, q.y, q.ia, o.x, o.y, o.ia, dq);
+            const double d = acosh1p(t, sh);
+            c += p * (log(p) + log1p(d * d));
+        }
+    }
+    c = group_sum<kKlLanes>(c);
+    if (sub == 0) s_row[threadIdx.x / kKlLanes] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = 0.0;
+        for (int r = 0; r < kBlock / kKlLanes; ++r) b += s_row[r];
+        part[blockIdx.x] = b;
+    }
+}
+
+// one workgroup: the block sums in a fixed order, plus ln Z
+__global__ __launch_bounds__(kBlock) void k_kl_final(const double *__restrict__ part, int64_t nparts,
+                                                     const double *__restrict__ z_dev,
+                                                     double *__restrict__ kl_dev) {
+    __shared__ double sh[kBlock];
+    double s = 0.0;
+    for (int64_t a = threadIdx.x; a < nparts; a += kBlock) s += part[a];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *kl_dev = sh[0] + log(*z_dev);
+}
+
+int64_t kl_parts(int64_t n) { return cdiv(n * kKlLanes, kBlock); }
+
+template <typename T>
+hts_status launch_kl(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, const int64_t *rp,
+                     const int32_t *col, const T *val, int64_t n, double ex, double *part,
+                     const double *z_dev, double *kl_dev) {
+    const int64_t nb = kl_parts(n);
+    hipLaunchKernelGGL(k_kl_rows<T>, dim3(nb), dim3(kBlock), 0, st, pts, rp, col, val, n, ex, part,
+                       ctx->d_err);
+    hipLaunchKernelGGL(k_kl_final, dim3(1), dim3(kBlock), 0, st, part, nb, z_dev, kl_dev);
+    HTS_HIP(hipGetLastError());
+    return HTS_OK;
+}
+
+// ---------------------------------------------------------------- exact call
+// Device memory of one exact-gradient call: point records, attractive
+// forces, repulsive forces, Z partials, the repulsion's chunk partials and the
+// cost's block sums.  Either the context's grow-on-demand workspaces or
+// consecutive pieces of one fixed region (exact_carve).
+static size_t ws_round(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// bytes of the pieces of an exact call on n points (each rounded to 256)
+template <typename T>
+size_t exact_ws_bytes(int64_t n, size_t sizes[6]) {
+    sizes[0] = ws_round((size_t)n * sizeof(PointRec<T>));
+    sizes[1] = ws_round((size_t)n * 2 * sizeof(T));
+    sizes[2] = ws_round((size_t)n * 2 * sizeof(double));
+    sizes[3] = ws_round((size_t)(cdiv(n, kBlock) + 8) * sizeof(double));
+    sizes[4] = ws_round(exact_part_bytes(n));
+    sizes[5] = ws_round((size_t)kl_parts(n) * sizeof(double));
+    size_t tot = 0;
+    for (int a = 0; a < 6; ++a) tot += sizes[a];
+    return tot;
+}
+
+template <typename T>
+ExactWs exact_carve(char *base, int64_t n) {
+    size_t sz[6];
+    exact_ws_bytes<T>(n, sz);
+    ExactWs w;
+    w.pts = base;
+    w.fattr = base + sz[0];
+    w.frep = (double *)(base + sz[0] + sz[1]);
+    w.zpart = (double *)(base + sz[0] + sz[1] + sz[2]);
+    w.part = (double *)(base + sz[0] + sz[1] + sz[2] + sz[3]);
+    w.klpart = (double *)(base + sz[0] + sz[1] + sz[2] + sz[3] + sz[4]);
+    return w;
+}
+
+// timed: the launches carry the context's timing events when timing is on
+template <typename T>
+hts_status exact_impl(hts_ctx c, hipStream_t st, const T *Y, int64_t n, const int64_t *rp,
+                             const int32_t *col, const T *val, double ex, T *grad, double *z_dev,
+                             double *kl_dev, const ExactWs &w, bool timed) {
+    PointRec<T> *pts = (PointRec<T> *)w.pts;
+    HTS_OKR(launch_prep_points<T>(c, st, Y, n, pts));
+    HTS_OKR(launch_attract<T>(c, st, pts, rp, col, val, n, (T *)w.fattr, timed));
+    int64_t nz = 0;
+    HTS_OKR(launch_exact<T>(c, st, pts, n, w.part, w.frep, w.zpart, &nz, timed));
+    HTS_OKR((launch_finalize<T, double>(c, st, (const T *)w.fattr, w.frep, w.zpart, nz, n, ex, grad,
+                                        z_dev, timed)));
+    if (kl_dev) HTS_OKR(launch_kl<T>(c, st, pts, rp, col, val, n, ex, w.klpart, z_dev, kl_dev));
     return HTS_OK;
 }
 
@@ -274,7 +415,7 @@ hts_status launch_step(hts_ctx ctx, hipStream_t st, T *Y, T *U, T *G, const T *g
 }
 
 // ---------------------------------------------------------------- CO-SNE
-// Sec. 3: gradient of lambda1 KL + (lambda2 / n) sum (|x_i|^2 - |y_i|^2)^2
+// Sec. 4-C: gradient of lambda1 KL + (lambda2 / n) sum (|x_i|^2 - |y_i|^2)^2
 // from the KL gradient in grad, in place:
 //   grad_i <- lambda1 grad_i - (4 lambda2 / n)(|x_i|^2 - |y_i|^2) y_i
 template <typename T>
@@ -308,21 +449,29 @@ hts_status launch_cosne(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, cons
                                               PointRec<T> *);                                    \
     template hts_status launch_attract<T>(hts_ctx, hipStream_t, const PointRec<T> *,              \
                                           const int64_t *, const int32_t *, const T *, int64_t,   \
-                                          T *);                                                  \
+                                          T *, bool);                                            \
     template hts_status launch_exact<T>(hts_ctx, hipStream_t, const PointRec<T> *, int64_t,       \
-                                        double *, double *, int64_t *);                          \
+                                        double *, double *, double *, int64_t *, bool);          \
     template hts_status launch_finalize<T, T>(hts_ctx, hipStream_t, const T *, const T *,         \
                                               const double *, int64_t, int64_t, double, T *,      \
-                                              double *);                                         \
+                                              double *, bool);                                   \
+    template hts_status launch_kl<T>(hts_ctx, hipStream_t, const PointRec<T> *, const int64_t *,  \
+                                     const int32_t *, const T *, int64_t, double, double *,       \
+                                     const double *, double *);                                  \
     template hts_status launch_cosne<T>(hts_ctx, hipStream_t, const T *, int64_t,                \
                                         const double *, double, double, T *);                     \
     template hts_status launch_step<T>(hts_ctx, hipStream_t, T *, T *, T *, const T *, int64_t,   \
                                        double, double, const int32_t *, const double *,          \
-                                       const double *, double, double, int);
+                                       const double *, double, double, int);                     \
+    template size_t exact_ws_bytes<T>(int64_t, size_t *);                                       \
+    template ExactWs exact_carve<T>(char *, int64_t);                                           \
+    template hts_status exact_impl<T>(hts_ctx, hipStream_t, const T *, int64_t, const int64_t *, \
+                                      const int32_t *, const T *, double, T *, double *, double *, \
+                                      const ExactWs &, bool);
 HTS_INST(float)
 HTS_INST(double)
 template hts_status launch_finalize<float, double>(hts_ctx, hipStream_t, const float *,
                                                    const double *, const double *, int64_t,
-                                                   int64_t, double, float *, double *);
+                                                   int64_t, double, float *, double *, bool);
 
 }  // namespace hts

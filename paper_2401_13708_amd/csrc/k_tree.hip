@@ -559,7 +559,7 @@ hts_status tree_sort_bytes(int64_t n_max, int L, size_t *bytes) {
 }
 
 // ---------------------------------------------------------------- Euclidean summaries
-// For the Euclidean Student-t term of h-SNE (Sec. 3) the same tree is walked
+// For the Euclidean Student-t term of h-SNE (Sec. 4-C) the same tree is walked
 // with Euclidean cell summaries: the centre of mass of a cell's points (from
 // double-double prefix sums of the sorted coordinates) and the criterion
 // ediam / |y - c| < theta, tested as |y - c|^2 > (ediam / theta)^2 with the

@@ -49,7 +49,7 @@ class Embedding:
         self.update = torch.zeros_like(self.Y)
         self.gains = torch.ones_like(self.Y)
         self.grad = torch.empty_like(self.Y)
-        # h-SNE (Sec. 3): Euclidean term plus hsne_lambda times the hyperbolic
+        # h-SNE (Sec. 4-C): Euclidean term plus hsne_lambda times the hyperbolic
         # one (Barnes-Hut only); z then holds Z^E and Z^H
         self.hsne_lambda = hsne_lambda
         if hsne_lambda is not None and exact:

@@ -44,7 +44,7 @@ _SIGS = {
     "hts_tree_destroy": (C.c_int, [_P]),
     "hts_build_polar_tree": (C.c_int, [_P, _P, _P, _I64, _I32, _P]),
     "hts_tree_export": (C.c_int, [_P, _P, _P, C.POINTER(_I64), _I64, _P, _P, _P, _P, _P, _P, _P]),
-    "hts_gradient_exact": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _P]),
+    "hts_gradient_exact": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _P, _P]),
     "hts_gradient_bh": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _D, _P, _P, _P]),
     "hts_gradient_hsne": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _D, _P, _D, _P, _P,
                                     _P]),
@@ -58,6 +58,7 @@ _SIGS = {
     "hts_set_item_list": (C.c_int, [_P, _I32]),
     "hts_cosne_terms": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _D, _D, _P]),
     "hts_tree_set_split": (C.c_int, [_P, _I32]),
+    "hts_workspace_generation": (C.c_int, [_P, C.POINTER(C.c_uint64)]),
     "hts_timing_enable": (C.c_int, [_P, _I32]),
     "hts_timing_read": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_I64)]),
 }
@@ -121,6 +122,11 @@ def _dev(t: torch.Tensor, name: str, dtype=None):
     return t
 
 
+# traversal counters of one Barnes-Hut call (include/hts.h): six for the whole
+# traversal (tests, accepted cells, leaf pairs, wave visits, visits with work,
+# points covered), then the same six for its second kernel
+STATS_BLOCK = 6
+STATS_PER_CALL = 2 * STATS_BLOCK
 DEFAULT_ITEM_POINTS = 256  # the library's default work-item size
 DEFAULT_ITEM_LIST = 256    # the library's default item-list entries per phase-A wave
 
@@ -163,6 +169,13 @@ class Context:
         """Barnes-Hut work-item size (a tuning parameter)."""
         _ck(lib().hts_set_item_points(self.h, int(s)))
         self.item_points = int(s)
+
+    def generation(self) -> int:
+        """Workspace generation: changes when device memory that earlier
+        launches referenced is reallocated (captured graphs are then stale)."""
+        g = C.c_uint64(0)
+        _ck(lib().hts_workspace_generation(self.h, C.byref(g)))
+        return int(g.value)
 
     # ------------------------------------------------------------ timing
     def timing(self, on: bool):
@@ -262,14 +275,18 @@ def _csr_args(Y, row_ptr, col_idx, p_val):
 
 
 def gradient_exact(ctx: Context, Y, row_ptr, col_idx, p_val, exaggeration: float = 1.0,
-                   grad=None, z=None, stream=None):
+                   grad=None, z=None, kl=None, stream=None):
+    """Exact gradient into grad and Z into z; the cost of eq. (3) into kl (a
+    device float64 tensor of one entry) when given."""
     _dev(Y, "Y")
     _csr_args(Y, row_ptr, col_idx, p_val)
     grad = torch.empty_like(Y) if grad is None else grad
     z = torch.empty(1, dtype=torch.float64, device=Y.device) if z is None else z
+    if kl is not None:
+        _dev(kl, "kl", torch.float64)
     _ck(lib().hts_gradient_exact(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
                                  _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), float(exaggeration),
-                                 _ptr(grad), _ptr(z)))
+                                 _ptr(grad), _ptr(z), _ptr(kl)))
     return grad, z
 
 
@@ -281,8 +298,8 @@ def gradient_bh(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, theta: flo
     z = torch.empty(1, dtype=torch.float64, device=Y.device) if z is None else z
     if stats is not None:
         _dev(stats, "stats", torch.int64)
-        if stats.numel() < 10:
-            raise ValueError("stats needs 10 int64 entries")
+        if stats.numel() < STATS_PER_CALL:
+            raise ValueError("stats needs %d int64 entries" % STATS_PER_CALL)
     _ck(lib().hts_gradient_bh(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
                               _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), float(exaggeration),
                               tree.h, float(theta), _ptr(grad), _ptr(z), _ptr(stats)))
@@ -292,18 +309,18 @@ def gradient_bh(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, theta: flo
 def gradient_hsne(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, lam: float,
                   theta: float = 0.5, exaggeration: float = 1.0, grad=None, z=None, stats=None,
                   stream=None):
-    """h-SNE gradient (Sec. 3): the Euclidean Student-t gradient of the disk
+    """h-SNE gradient (Sec. 4-C): the Euclidean Student-t gradient of the disk
     coordinates plus lam times the hyperbolic one, both Barnes-Hut over the
     tree.  z (device float64[2]) receives Z^E and Z^H; stats, if given, holds
-    20 int64 counters (Euclidean traversal, then hyperbolic)."""
+    24 int64 counters (Euclidean traversal, then hyperbolic)."""
     _dev(Y, "Y")
     _csr_args(Y, row_ptr, col_idx, p_val)
     grad = torch.empty_like(Y) if grad is None else grad
     z = torch.empty(2, dtype=torch.float64, device=Y.device) if z is None else z
     if stats is not None:
         _dev(stats, "stats", torch.int64)
-        if stats.numel() < 20:
-            raise ValueError("stats needs 20 int64 entries")
+        if stats.numel() < 2 * STATS_PER_CALL:
+            raise ValueError("stats needs %d int64 entries" % (2 * STATS_PER_CALL))
     _ck(lib().hts_gradient_hsne(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
                                 _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), float(exaggeration),
                                 float(lam), tree.h, float(theta), _ptr(grad), _ptr(z),
@@ -334,8 +351,8 @@ def gradient_bh_jobs(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, exagg
     z = torch.empty(nj, dtype=torch.float64, device=Y.device) if z is None else z
     if stats is not None:
         _dev(stats, "stats", torch.int64)
-        if stats.numel() < 10:
-            raise ValueError("stats needs 10 int64 entries")
+        if stats.numel() < STATS_PER_CALL:
+            raise ValueError("stats needs %d int64 entries" % STATS_PER_CALL)
     _ck(lib().hts_gradient_bh_jobs(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
                                    _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), _ptr(exaggeration),
                                    tree.h, float(theta), _ptr(grad), _ptr(z), _ptr(stats)))

@@ -121,7 +121,7 @@ def _bh_against_oracle(ctx, n, stage, theta, ex, csr_seed):
     Y = embedding(n, stage, np.float32)
     rp, col, v32 = synth.random_csr(n, 90, seed=csr_seed, dtype=np.float32)
     g, z = _bh(ctx, Y, rp, col, v32, theta, ex)
-    st = torch.zeros(10, dtype=torch.int64, device="cuda")
+    st = torch.zeros(hts.STATS_PER_CALL, dtype=torch.int64, device="cuda")
     g2, z2 = _bh(ctx, Y, rp, col, v32, theta, ex, stats=st)
     # the counting variant computes the same result
     assert np.array_equal(g, g2) and z == z2
@@ -134,6 +134,9 @@ def _bh_against_oracle(ctx, n, stage, theta, ex, csr_seed):
     s = st.cpu().numpy()
     for a, key in enumerate(("tests", "accepts", "pairs")):
         assert abs(int(s[a]) - cnt[key]) <= 1e-4 * cnt[key] + 64, key
+    # whichever cells the criterion takes, each query accounts for every other
+    # point exactly once (an identity that holds at any size)
+    assert int(s[5]) == cnt["covered"] == n * (n - 1)
 
 
 @pytest.mark.parametrize("stage", ["init", "mid", "late", "edge"])

@@ -34,7 +34,7 @@ def _run_bh(ctx, Y, rp, col, val, ex, theta, max_depth=20, stats=False, split=0)
     if split:
         tree.set_split(split)
     hts.build_polar_tree(ctx, Yd, tree)
-    st = torch.zeros(10, dtype=torch.int64, device="cuda") if stats else None
+    st = torch.zeros(hts.STATS_PER_CALL, dtype=torch.int64, device="cuda") if stats else None
     g, z = hts.gradient_bh(ctx, Yd, _dev(rp), _dev(col), _dev(val), tree, theta, ex, stats=st)
     torch.cuda.synchronize()
     assert ctx.check() == 0
@@ -68,6 +68,58 @@ def test_exact_f32(ctx, stage, n):
     assert z == pytest.approx(zo, rel=1e-5)
 
 
+def _exact_kl(ctx, Y, rp, col, val, ex):
+    kl = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g, z = hts.gradient_exact(ctx, _dev(Y), _dev(rp), _dev(col), _dev(val), ex, kl=kl)
+    torch.cuda.synchronize()
+    assert ctx.check() == 0
+    return g.cpu().numpy(), float(z.cpu()[0]), float(kl.cpu()[0])
+
+
+@pytest.mark.parametrize("stage", STAGES)
+@pytest.mark.parametrize("ex", [12.0, 1.0])
+def test_exact_cost_f64(ctx, stage, ex):
+    # the optional cost output of eq. (3) against the oracle's; the gradient
+    # and Z are those of the call without it
+    X, _, rp, col, val = affinities(1000)
+    Y = embedding(1000, stage, np.float64)
+    g, z, kl = _exact_kl(ctx, Y, rp, col, val, ex)
+    g0, z0 = _run_exact(ctx, Y, rp, col, val, ex)
+    assert np.array_equal(g, g0) and z == z0
+    want = oracle.kl_cost(Y, rp, col, val, ex)
+    assert kl == pytest.approx(want, rel=1e-10)
+
+
+@pytest.mark.parametrize("stage", STAGES)
+@pytest.mark.parametrize("n", [1000, 1337])
+def test_exact_cost_f32(ctx, stage, n):
+    X, _, rp, col, val = affinities(n)
+    Y = embedding(n, stage, np.float32)
+    v32 = val.astype(np.float32)
+    _, _, kl = _exact_kl(ctx, Y, rp, col, v32, 1.0)
+    want = oracle.kl_cost(Y.astype(np.float64), rp, col, v32.astype(np.float64), 1.0)
+    assert kl == pytest.approx(want, rel=1e-5)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("ex", [1.0, 12.0])
+def test_exact_cost_two_points(ctx, dtype, ex):
+    # the two-point closed form: ex ln ex - (ex - 1)(ln 2 + ln w), w from
+    # d = 4 artanh a between (a, 0) and (-a, 0); zero for ex = 1
+    a = 0.5
+    Y = np.array([[a, 0.0], [-a, 0.0]], dtype=dtype)
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    col = np.array([1, 0], dtype=np.int32)
+    val = np.array([0.5, 0.5], dtype=dtype)
+    _, z, kl = _exact_kl(ctx, Y, rp, col, val, ex)
+    d = 4.0 * np.arctanh(float(Y[0, 0]))
+    w = 1.0 / (1.0 + d * d)
+    want = ex * np.log(ex) - (ex - 1.0) * (np.log(2.0) + np.log(w))
+    tol = 1e-6 if dtype == np.float32 else 1e-13
+    assert kl == pytest.approx(want, rel=tol, abs=tol)
+    assert z == pytest.approx(2 * w, rel=tol)
+
+
 @pytest.mark.parametrize("n", [2, 3, 65, 257])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_exact_small_sizes(ctx, n, dtype):
@@ -93,6 +145,7 @@ def test_bh_theta0_equals_exact(ctx, stage):
     assert rel(g, go) < 1e-10
     assert z == pytest.approx(zo, rel=1e-12)
     assert st[1] == 0 and st[2] == 1000 * 999
+    assert st[5] == 1000 * 999
 
 
 @pytest.mark.parametrize("stage", STAGES)
@@ -103,8 +156,10 @@ def test_bh_f64_matches_oracle_bh(ctx, stage):
     t = oracle.Tree(Y)
     go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 1.0)
     assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    # every query accounts for each other point once, through a cell or a pair
+    assert st[5] == cnt["covered"] == 1000 * 999
     # the share of the second traversal kernel is part of the totals
-    assert all(0 <= b <= a for a, b in zip(st[:5], st[5:]))
+    assert all(0 <= b <= a for a, b in zip(st[:6], st[6:]))
     assert rel(g, go) < 1e-10
     # an accepted cell's midpoint carries the rounding of its sums, amplified
     # by 1 / (1 - |m|^2) near the rim
@@ -156,6 +211,7 @@ def test_bh_equal_area_matches_oracle_bh(ctx, stage):
     t = oracle.Tree(Y, split_rule=1)
     go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 12.0)
     assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    assert st[5] == cnt["covered"]
     assert rel(g, go) < 1e-10
     assert z == pytest.approx(zo, rel=1e-10)
 
@@ -163,7 +219,7 @@ def test_bh_equal_area_matches_oracle_bh(ctx, stage):
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("theta", [0.0, 0.5])
 def test_cosne_terms_match_oracle(ctx, dtype, theta):
-    # CO-SNE (Sec. 3) on top of the Barnes-Hut (theta = 0.5) or exact
+    # CO-SNE (Sec. 4-C) on top of the Barnes-Hut (theta = 0.5) or exact
     # (theta = 0) KL gradient, against the oracle's at the same theta
     X, _, rp, col, val = affinities(1000)
     Y = embedding(1000, "late", dtype)
@@ -190,6 +246,7 @@ def test_bh_large_theta_root_accepted(ctx, theta):
     t = oracle.Tree(Y)
     go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, theta, 1.0)
     assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    assert st[5] == cnt["covered"]
     assert rel(g, go) < 1e-10
     assert z == pytest.approx(zo, rel=1e-10)
 
@@ -209,6 +266,7 @@ def test_bh_work_item_sizes(ctx, item_points):
     t = oracle.Tree(Y)
     go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 12.0)
     assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    assert st[5] == cnt["covered"]
     assert rel(g, go) < 1e-10
     assert z == pytest.approx(zo, rel=1e-10)
 
@@ -232,8 +290,9 @@ def test_bh_item_list_sizes(ctx, item_list, item_points):
     t = oracle.Tree(Y)
     go, zo, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 12.0)
     assert st[:3] == [cnt["tests"], cnt["accepts"], cnt["pairs"]]
+    assert st[5] == cnt["covered"]
     if item_list == 0:
-        assert st[5:] == [0, 0, 0, 0, 0]
+        assert st[6:] == [0] * 6
     assert rel(g, go) < 1e-10
     assert z == pytest.approx(zo, rel=1e-10)
     assert np.array_equal(g, g2) and z == z2

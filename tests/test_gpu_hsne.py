@@ -1,4 +1,4 @@
-"""h-SNE gradient (Sec. 3) on the GPU against the FP64 oracle on shared seeded
+"""h-SNE gradient (Sec. 4-C) on the GPU against the FP64 oracle on shared seeded
 inputs: the Euclidean Student-t part of the disk coordinates over the polar
 quadtree (centres of mass, Euclidean criterion) plus lambda times the
 hyperbolic part.
@@ -27,7 +27,7 @@ def _run(ctx, Y, rp, col, val, ex, lam, theta, max_depth=20, stats=False):
     Yd = _dev(Y)
     tree = hts.Tree(ctx, Y.shape[0], max_depth)
     hts.build_polar_tree(ctx, Yd, tree)
-    st = torch.zeros(20, dtype=torch.int64, device="cuda") if stats else None
+    st = torch.zeros(2 * hts.STATS_PER_CALL, dtype=torch.int64, device="cuda") if stats else None
     g, z = hts.gradient_hsne(ctx, Yd, _dev(rp), _dev(col), _dev(val), tree, lam, theta, ex,
                              stats=st)
     torch.cuda.synchronize()
@@ -55,7 +55,8 @@ def test_hsne_f64_matches_oracle(ctx, stage, theta):
     g, z, st = _run(ctx, Y, rp, col, val, 12.0, 0.7, theta, stats=True)
     go, ze, zh, ce, ch = _oracle(Y, rp, col, val, 12.0, 0.7, theta)
     assert st[:3] == [ce["tests"], ce["accepts"], ce["pairs"]]
-    assert st[10:13] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    assert st[12:15] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    assert st[5] == ce["covered"] and st[17] == ch["covered"]
     if theta > 0:
         assert ce["accepts"] > 0
     assert rel(g, go) < 1e-10
@@ -237,7 +238,8 @@ def test_hsne_work_item_sizes_and_large_theta(ctx, item_points, theta):
         ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
     go, ze, zh, ce, ch = _oracle(Y, rp, col, val, 12.0, 0.6, theta)
     assert st[:3] == [ce["tests"], ce["accepts"], ce["pairs"]]
-    assert st[10:13] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    assert st[12:15] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    assert st[5] == ce["covered"] and st[17] == ch["covered"]
     assert rel(g, go) < 1e-10
     assert z[0] == pytest.approx(ze, rel=1e-10)
 
@@ -256,7 +258,8 @@ def test_hsne_short_item_list(ctx, item_list):
         ctx.set_item_list(hts.DEFAULT_ITEM_LIST)
     go, ze, zh, ce, ch = _oracle(Y, rp, col, val, 12.0, 0.6, 0.5)
     assert st[:3] == [ce["tests"], ce["accepts"], ce["pairs"]]
-    assert st[10:13] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    assert st[12:15] == [ch["tests"], ch["accepts"], ch["pairs"]]
+    assert st[5] == ce["covered"] and st[17] == ch["covered"]
     assert rel(g, go) < 1e-10
     assert z[0] == pytest.approx(ze, rel=1e-10)
     assert z[1] == pytest.approx(zh, rel=1e-10)

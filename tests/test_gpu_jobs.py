@@ -253,3 +253,55 @@ def test_graph_replays_equal_eager_iterations(ctx):
     assert ctx.check() == 0
     eager.close()
     b.close()
+
+
+def test_set_jobs_rejects_job_bits_beyond_the_key(ctx):
+    # the job index sits above the 2 max_depth cell bits of a 64-bit key:
+    # at depth 24, 2^16 jobs fill the key exactly and one more cannot fit
+    t = hts.Tree(ctx, 2 * (1 << 16) + 2, 24)
+    with pytest.raises(hts.HTSError, match="key bits"):
+        t.set_jobs([2] * ((1 << 16) + 1))
+    t.set_jobs([2] * (1 << 16))
+    t.close()
+
+
+def test_graph_recaptured_after_workspace_growth():
+    # a captured batch iteration points into the context's workspaces; when a
+    # later call on the context grows one (here an exact gradient of a larger
+    # embedding), the next iteration runs eagerly and is captured again
+    # instead of replaying into freed memory, and every iteration still
+    # equals the eager run
+    c = hts.Context(0)
+    sizes = [500, 65, 1200]
+    jobs = []
+    for j, n in enumerate(sizes):
+        Y0 = synth.disk_uniform(n, 1e-4, seed=130 + j)
+        rp, col, val = synth.random_csr(n, min(30, n - 1), seed=135 + j, dtype=np.float32)
+        jobs.append(Job(_d(rp), _d(col), _d(val), _d(Y0)))
+    eager = JobBatch(c, jobs)
+    want = []
+    for _ in range(8):
+        eager.iterate()
+        want.append(eager.Y.clone())
+    eager.close()
+    b = JobBatch(c, jobs).capture()
+    assert torch.equal(b.Y, want[0])
+    g0 = c.generation()
+    for k in (1, 2, 3):
+        b.iterate()
+        torch.cuda.synchronize()
+        assert torch.equal(b.Y, want[k]), k
+    n = 30000
+    Yl = _d(synth.disk_state(n, "mid", seed=140))
+    rp, col, val = synth.random_csr(n, 30, seed=141, dtype=np.float32)
+    hts.gradient_exact(c, Yl, _d(rp), _d(col), _d(val), 1.0)
+    torch.cuda.synchronize()
+    assert c.generation() != g0
+    for k in range(4, 8):
+        b.iterate()
+        torch.cuda.synchronize()
+        assert torch.equal(b.Y, want[k]), k
+    assert b.graph_gen == c.generation()
+    assert c.check() == 0
+    b.close()
+    c.close()

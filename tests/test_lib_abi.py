@@ -36,10 +36,10 @@ def test_library_is_gfx950_code():
                                  None, None), "n = 1 < 2"),
     (lambda L: L.hts_gradient_exact(None, None, C.c_void_p(8), 10, 7, C.c_void_p(8),
                                     C.c_void_p(8), C.c_void_p(8), 1.0, C.c_void_p(8),
-                                    C.c_void_p(8)), "bad dtype"),
+                                    C.c_void_p(8), None), "bad dtype"),
     (lambda L: L.hts_gradient_exact(None, None, C.c_void_p(8), 10, 0, C.c_void_p(8),
                                     C.c_void_p(8), C.c_void_p(8), 0.0, C.c_void_p(8),
-                                    C.c_void_p(8)), "exaggeration"),
+                                    C.c_void_p(8), None), "exaggeration"),
     (lambda L: L.hts_gradient_bh(None, None, C.c_void_p(8), 10, 0, C.c_void_p(8), C.c_void_p(8),
                                  C.c_void_p(8), 1.0, C.c_void_p(8), -0.5, C.c_void_p(8),
                                  C.c_void_p(8), None), "ctx is NULL"),
@@ -57,6 +57,7 @@ def test_library_is_gfx950_code():
     (lambda L: L.hts_tree_create(None, 100, 40, C.byref(C.c_void_p())), "max_depth"),
     (lambda L: L.hts_tree_create(None, 3_195_661, 20, C.byref(C.c_void_p())), "2^26"),
     (lambda L: L.hts_build_polar_tree(None, None, None, 10, 0, None), "NULL handle"),
+    (lambda L: L.hts_workspace_generation(None, C.byref(C.c_uint64())), "NULL argument"),
 ])
 def test_host_validation(call, msg):
     L = hts.lib()

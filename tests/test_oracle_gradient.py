@@ -154,7 +154,7 @@ def test_bh_error_band_and_growth():
     assert lo / 30 < errs[0.5] < hi * 10, (errs, lo, hi)
 
 
-# ---------------------------------------------------------------- CO-SNE (Sec. 3)
+# ---------------------------------------------------------------- CO-SNE (Sec. 4-C)
 def _fd(fun, Y):
     fd = np.zeros_like(Y)
     for i in range(Y.shape[0]):
@@ -193,3 +193,106 @@ def test_cosne_printed_sign_fails_fd():
     xs = np.sum(Z * Z, 1)
     zero = oracle.cosne_gradient(Z, xs, 0.0, lam2, gk)
     assert np.abs(zero).max() < 1e-15
+
+
+# ---------------------------------------------------------------- further pins
+@pytest.mark.parametrize("stage,ex", [("early", 12.0), ("mid", 1.0), ("edge", 1.0)])
+def test_exact_rows_equal_the_whole_gradient(stage, ex):
+    # the row-subset routine (used where the whole O(n^2) gradient is too
+    # slow) against the whole gradient, all rows, at three stages
+    Y, rp, col, val = _problem(53, seed=21, stage=stage)
+    g, z = oracle.gradient_exact(Y, rp, col, val, ex)
+    rows = np.arange(Y.shape[0])
+    gr = oracle.gradient_exact_rows(Y, rp, col, val, rows, z, ex)
+    assert np.allclose(gr, g, rtol=1e-13, atol=1e-15 * np.abs(g).max())
+    # and on a shuffled subset, each row where it belongs
+    sub = synth.rng(22).permutation(Y.shape[0])[:17]
+    gs = oracle.gradient_exact_rows(Y, rp, col, val, sub, z, ex)
+    assert np.allclose(gs, g[sub], rtol=1e-13, atol=1e-15 * np.abs(g).max())
+
+
+def _two_point_csr():
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    col = np.array([1, 0], dtype=np.int32)
+    val = np.array([0.5, 0.5])
+    return rp, col, val
+
+
+@pytest.mark.parametrize("a", [0.1, 0.5, 0.9])
+@pytest.mark.parametrize("ex", [1.0, 2.0, 12.0])
+def test_kl_cost_two_point_closed_form(a, ex):
+    # two points at (a, 0) and (-a, 0): by symmetry about the origin their
+    # distance is twice d(0, (a, 0)) = 2 artanh a, so d = 4 artanh a (eq. (8)),
+    # w = (1 + d^2)^-1, Z = 2 w and q_12 = q_21 = 1/2 = p_12 = p_21.  The cost
+    # sum ex p ln(ex p) - sum ex p ln w + ln Z is then
+    # ex ln ex - (ex - 1)(ln 2 + ln w), which vanishes at ex = 1 (Q = P)
+    Y = np.array([[a, 0.0], [-a, 0.0]])
+    rp, col, val = _two_point_csr()
+    d = 4.0 * np.arctanh(a)
+    w = 1.0 / (1.0 + d * d)
+    want = ex * np.log(ex) - (ex - 1.0) * (np.log(2.0) + np.log(w))
+    got = oracle.kl_cost(Y, rp, col, val, ex)
+    assert got == pytest.approx(want, rel=1e-13, abs=1e-14)
+    if ex == 1.0:
+        assert abs(got) < 1e-14
+
+
+@pytest.mark.parametrize("stage", ["early", "mid", "late"])
+@pytest.mark.parametrize("ex", [1.0, 12.0])
+def test_kl_cost_dense_definition(stage, ex):
+    # eq. (3) written out over dense matrices with numpy: q_ij = w_ij / Z from
+    # arccosh of the eq. (8) argument, KL = sum p ln(p / q) for ex = 1, and in
+    # general sum ex p ln(ex p) - sum ex p ln w + ln Z
+    Y, rp, col, val = _problem(40, seed=23, stage=stage)
+    n = Y.shape[0]
+    P = np.zeros((n, n))
+    for i in range(n):
+        P[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    sq = np.sum(Y * Y, axis=1)
+    D2 = np.sum((Y[:, None, :] - Y[None, :, :]) ** 2, axis=-1)
+    gam = 1.0 + 2.0 * D2 / ((1.0 - sq)[:, None] * (1.0 - sq)[None, :])
+    W = 1.0 / (1.0 + np.arccosh(gam) ** 2)
+    np.fill_diagonal(W, 0.0)
+    Z = W.sum()
+    nz = P > 0
+    if ex == 1.0:
+        want = np.sum(P[nz] * np.log(P[nz] / (W[nz] / Z)))
+    else:
+        A = ex * P[nz]
+        want = np.sum(A * np.log(A)) - np.sum(A * np.log(W[nz])) + np.log(Z)
+    assert oracle.kl_cost(Y, rp, col, val, ex) == pytest.approx(want, rel=1e-11)
+
+
+@pytest.mark.parametrize("stage", ["init", "early", "mid", "late", "edge"])
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.8, 0.99, 1.5])
+def test_bh_accounts_for_every_point_once(stage, theta):
+    # whichever cells the criterion accepts, every query stands for each other
+    # point exactly once: sum of N_cell over accepted cells + leaf pairs =
+    # n (n - 1).  A cell counted twice, a skipped child or a leaf that keeps
+    # the query itself breaks the identity.  Below theta = 1 no cell holding
+    # the query can be accepted (its distance to the cell's midpoint or centre
+    # of mass is at most the cell's diameter); from theta = 1 on such a cell
+    # may stand for the query too, once per level at most.
+    Y, rp, col, val = _problem(97, seed=31, stage=stage)
+    n = Y.shape[0]
+    t = oracle.Tree(Y)
+    _, _, cnt = oracle.gradient_bh(Y, rp, col, val, t, theta, 1.0)
+    _, _, ce = oracle.gradient_euclid_bh(Y, rp, col, val, t, theta, 1.0)
+    if theta >= 0.5 and stage != "init":
+        assert cnt["accepts"] > 0
+    for c in (cnt, ce):
+        if theta < 1.0:
+            assert c["covered"] == n * (n - 1)
+        else:
+            assert n * (n - 1) <= c["covered"] <= n * (n - 1) + n * 20
+
+
+def test_bh_accounts_for_every_point_once_with_duplicates_and_depth_cap():
+    # duplicate points end in depth-capped leaves holding several points
+    Y, rp, col, val = _problem(64, seed=33, stage="mid")
+    Y[10:20] = Y[3]
+    n = Y.shape[0]
+    for depth in (3, 20):
+        t = oracle.Tree(Y, max_depth=depth)
+        _, _, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 1.0)
+        assert cnt["covered"] == n * (n - 1)

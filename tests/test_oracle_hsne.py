@@ -1,4 +1,4 @@
-"""Pins of the oracle's h-SNE terms (Sec. 3): the Euclidean Student-t cost of
+"""Pins of the oracle's h-SNE terms (Sec. 4-C): the Euclidean Student-t cost of
 the disk coordinates and its exact gradient against finite differences and a
 two-point closed form; the combined h-SNE gradient against finite differences
 of KL(P||Q^E) + lambda KL(P||Q^H); the Barnes-Hut Euclidean gradient over the
