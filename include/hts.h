@@ -173,6 +173,24 @@ hts_status hts_gradient_exact(hts_ctx ctx, hts_stream stream, const void *Y,
                               double exaggeration, void *grad, double *z_dev,
                               double *kl_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid allocation): hts_gradient_exact with
+ * the same arguments, results and kernels, but every byte of workspace it
+ * needs comes from one fixed device region per GPU (18 MiB, held by each GPU
+ * the library runs on until the process ends) instead of the context's
+ * grow-on-demand buffers, so the call allocates and frees nothing and sets
+ * no timing events.  n <= HTS_NOALLOC_MAX_N, else HTS_ECAPACITY.  All calls
+ * on one GPU share the region and it keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other contexts, other
+ * threads) race and must not be issued. */
+#define HTS_NOALLOC_MAX_N 65536
+hts_status hts_gradient_exact_noalloc(hts_ctx ctx, hts_stream stream,
+                                      const void *Y, int64_t n, int32_t dtype,
+                                      const int64_t *row_ptr,
+                                      const int32_t *col_idx, const void *p_val,
+                                      double exaggeration, void *grad,
+                                      double *z_dev, double *kl_dev);
+
 /* Barnes-Hut repulsion (eq. (19)): a cell whose diameter r_cell and midpoint
  * m satisfy r_cell / d(y_i, m) < theta stands for its N_cell points;
  * theta = 0 evaluates every pair.  tree must have been built from the same Y.

@@ -45,6 +45,8 @@ _SIGS = {
     "hts_build_polar_tree": (C.c_int, [_P, _P, _P, _I64, _I32, _P]),
     "hts_tree_export": (C.c_int, [_P, _P, _P, C.POINTER(_I64), _I64, _P, _P, _P, _P, _P, _P, _P]),
     "hts_gradient_exact": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _P, _P]),
+    "hts_gradient_exact_noalloc": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _P,
+                                             _P]),
     "hts_gradient_bh": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _D, _P, _P, _P]),
     "hts_gradient_hsne": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _D, _P, _D, _P, _P,
                                     _P]),
@@ -287,6 +289,26 @@ def gradient_exact(ctx: Context, Y, row_ptr, col_idx, p_val, exaggeration: float
     _ck(lib().hts_gradient_exact(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
                                  _ptr(row_ptr), _ptr(col_idx), _ptr(p_val), float(exaggeration),
                                  _ptr(grad), _ptr(z), _ptr(kl)))
+    return grad, z
+
+
+NOALLOC_MAX_N = 65536  # HTS_NOALLOC_MAX_N of include/hts.h
+
+
+def gradient_exact_noalloc(ctx: Context, Y, row_ptr, col_idx, p_val, grad, z,
+                           exaggeration: float = 1.0, kl=None, stream=None):
+    """gradient_exact without any device allocation in the library: the
+    workspace is the library's fixed per-GPU region (n <= NOALLOC_MAX_N);
+    grad, z (and kl) are caller-owned device tensors."""
+    _dev(Y, "Y")
+    _csr_args(Y, row_ptr, col_idx, p_val)
+    _dev(grad, "grad", Y.dtype)
+    _dev(z, "z", torch.float64)
+    if kl is not None:
+        _dev(kl, "kl", torch.float64)
+    _ck(lib().hts_gradient_exact_noalloc(ctx.h, _stream(stream), _ptr(Y), Y.shape[0], _dtype(Y),
+                                         _ptr(row_ptr), _ptr(col_idx), _ptr(p_val),
+                                         float(exaggeration), _ptr(grad), _ptr(z), _ptr(kl)))
     return grad, z
 
 
