@@ -73,6 +73,9 @@ def lib():
         L.ora_tree_export.argtypes = [C.c_void_p, _I32, _I32, _I32, _I32, _D, _D, _D, _I64]
         L.ora_gradient_bh.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double, C.c_void_p,
                                       C.c_double, _D, _D, _I64]
+        L.ora_gradient_bh_rows.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double,
+                                           C.c_void_p, C.c_double, _I64, C.c_int64, C.c_double,
+                                           _D, _I64]
         L.ora_euclid_cost.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double, _D]
         L.ora_gradient_euclid_exact.argtypes = [_D, C.c_int64, _I64, _I32, _D, C.c_double, _D,
                                                 _D]
@@ -310,6 +313,21 @@ def gradient_bh(Y, rp, col, val, tree: Tree, theta: float, exaggeration: float =
                                  _p(cnt, _I64)), "gradient_bh")
     return g, float(z[0]), dict(tests=int(cnt[0]), accepts=int(cnt[1]), pairs=int(cnt[2]),
                                 covered=int(cnt[3]))
+
+
+def gradient_bh_rows(Y, rp, col, val, tree: Tree, theta: float, rows, z: float,
+                     exaggeration: float = 1.0):
+    """Barnes-Hut gradient rows of a subset of the queries, Z given."""
+    Y = _f64(Y).reshape(-1, 2)
+    rp, col, val = _csr(rp, col, val)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    g = np.zeros((rows.size, 2))
+    cnt = np.zeros(4, dtype=np.int64)
+    _check(lib().ora_gradient_bh_rows(_p(Y, _D), Y.shape[0], _p(rp, _I64), _p(col, _I32),
+                                      _p(val, _D), float(exaggeration), tree.h, float(theta),
+                                      _p(rows, _I64), rows.size, float(z), _p(g, _D),
+                                      _p(cnt, _I64)), "gradient_bh_rows")
+    return g, dict(tests=int(cnt[0]), accepts=int(cnt[1]), pairs=int(cnt[2]), covered=int(cnt[3]))
 
 
 # ---- h-SNE (Sec. 4-C): Euclidean Student-t term of the disk coordinates ----

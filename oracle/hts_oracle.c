@@ -485,6 +485,7 @@ int ora_gradient_exact_rows(const double *Y, int64_t n, const int64_t *row_ptr,
 
 typedef struct {
     double r_lo, r_hi, p_lo, p_hi; /* polar quadrilateral [r_lo,r_hi] x [p_lo,p_hi) */
+    double a_lo[2], a_hi[2];       /* directions of its two angular bounds (the split rays) */
     int32_t depth;
     int32_t child[4];              /* -1: empty sub-cell (no node) */
     int32_t count;                 /* points in the subtree */
@@ -498,7 +499,8 @@ struct ora_tree {
     int32_t max_depth;
     int32_t split_rule; /* 0: equal radial lengths, eq. (10); 1: equal areas, eq. (9) */
     double *px, *py;   /* point coordinates (full precision) */
-    double *r, *phi;   /* polar position of the FP32-rounded coordinates */
+    double *r;         /* radius of the FP32-rounded coordinates */
+    double *xs, *ys;   /* the FP32-rounded coordinates */
     onode *nodes;
     int64_t nn, capn;
     /* pre-order export, filled after the build */
@@ -511,20 +513,56 @@ struct ora_tree {
     double *ediam;     /* Euclidean cell diameters, pre-order (h-SNE term) */
 };
 
-/* reading: the angular position phi in [0, 2 pi) and the radius are taken
- * from the coordinates rounded to single precision, so that the tree depends
- * only on the stored single-precision embedding; phi = atan2(y, x) (+ 2 pi
- * when negative) and r = sqrt(x^2 + y^2), both in double precision. */
-static void polar_of(double x, double y, double *r, double *phi) {
-    double xs = (double)(float)x, ys = (double)(float)y;
-    *r = sqrt(xs * xs + ys * ys);
-    double p = atan2(ys, xs);
-    if (p < 0.0) p += 2.0 * M_PI;
-    *phi = p;
+/* reading: the radius and the angular position are taken from the
+ * coordinates rounded to single precision, so that the tree depends only on
+ * the stored single-precision embedding; r = sqrt(x^2 + y^2) in double (the
+ * products are exact, the sum and the root rounded once each). */
+static void polar_of(double x, double y, double *r, double *xs, double *ys) {
+    *xs = (double)(float)x;
+    *ys = (double)(float)y;
+    *r = sqrt(*xs * *xs + *ys * *ys);
+}
+
+/* The angular split of Sec. 2-D halves a cell's angular range at
+ * mid_phi = (max_phi + min_phi) / 2.  reading: the half is decided without
+ * computing the angle of the point (an angle from atan2 differs in its last
+ * bit between math libraries): the split ray of a cell is a direction
+ * vector built from those of its bounds -- the negative x-axis for the root
+ * (the ray at pi), the bound min_phi turned by a right angle at depth 1
+ * (widths pi), and below that the normalised sum of the two bound
+ * directions, each operation rounded on its own in double -- and a point
+ * (x, y) lies in the upper half iff c y - s x >= 0 with (c, s) that
+ * direction rounded to single precision.  With single-precision coordinates
+ * both products are exact in double and the one rounding of the difference
+ * keeps its sign, so the decision is exact; points on the ray go to the upper
+ * half, as phi >= mid_phi sends them.  The root: phi >= pi iff y < 0, or
+ * y = 0 and x < 0 (the origin takes the lower half there and the upper half
+ * below, where it lies on every ray). */
+static void ang_mid(int32_t depth, const double *lo, const double *hi, double *mid) {
+    if (depth == 0) {
+        mid[0] = -1.0;
+        mid[1] = 0.0;
+        return;
+    }
+    if (depth == 1) {
+        mid[0] = -lo[1];
+        mid[1] = lo[0];
+        return;
+    }
+    double sx = lo[0] + hi[0], sy = lo[1] + hi[1];
+    double h = sqrt(sx * sx + sy * sy);
+    mid[0] = sx / h;
+    mid[1] = sy / h;
+}
+
+static int ang_bit(int32_t depth, const double *mid, double xs, double ys) {
+    if (depth == 0) return ys < 0.0 || (ys == 0.0 && xs < 0.0);
+    double c = (double)(float)mid[0], s = (double)(float)mid[1];
+    return c * ys - s * xs >= 0.0;
 }
 
 static int32_t new_node(ora_tree *t, double rlo, double rhi, double plo,
-                        double phi, int32_t depth) {
+                        double phi, const double *alo, const double *ahi, int32_t depth) {
     if (t->nn == t->capn) {
         int64_t nc = t->capn ? 2 * t->capn : 64;
         onode *nb = (onode *)realloc(t->nodes, sizeof(onode) * (size_t)nc);
@@ -535,6 +573,8 @@ static int32_t new_node(ora_tree *t, double rlo, double rhi, double plo,
     onode *o = &t->nodes[t->nn];
     memset(o, 0, sizeof(*o));
     o->r_lo = rlo; o->r_hi = rhi; o->p_lo = plo; o->p_hi = phi;
+    o->a_lo[0] = alo[0]; o->a_lo[1] = alo[1];
+    o->a_hi[0] = ahi[0]; o->a_hi[1] = ahi[1];
     o->depth = depth;
     o->child[0] = o->child[1] = o->child[2] = o->child[3] = -1;
     o->is_leaf = 1;
@@ -558,25 +598,32 @@ double ora_radial_mid(double lo, double hi, int32_t rule) {
     return sqrt(sum / (2.0 + sum));
 }
 
-/* Split of a cell into four (Sec. 4-A): the angular range is halved,
- * mid_phi = (max_phi + min_phi) / 2 (Sec. 2-D), and the radial range at
- * ora_radial_mid.  Children are numbered 2 * [r >= mid_r] + [phi >= mid_phi]. */
-static int digit_of(const ora_tree *t, const onode *o, double r, double phi) {
+/* Split of a cell into four (Sec. 4-A): the angular range is halved at its
+ * split ray (ang_mid, ang_bit), and the radial range at ora_radial_mid.
+ * Children are numbered 2 * [r >= mid_r] + [upper angular half]. */
+static int digit_of(const ora_tree *t, const onode *o, int64_t p) {
     double mr = ora_radial_mid(o->r_lo, o->r_hi, t->split_rule);
-    double mp = (o->p_lo + o->p_hi) * 0.5;
-    return 2 * (r >= mr) + (phi >= mp);
+    double am[2];
+    ang_mid(o->depth, o->a_lo, o->a_hi, am);
+    return 2 * (t->r[p] >= mr) + ang_bit(o->depth, am, t->xs[p], t->ys[p]);
 }
 
 static int32_t child_of(ora_tree *t, int32_t nid, int64_t p) {
     onode *o = &t->nodes[nid];
-    int dg = digit_of(t, o, t->r[p], t->phi[p]);
+    int dg = digit_of(t, o, p);
     if (o->child[dg] >= 0) return o->child[dg];
     double mr = ora_radial_mid(o->r_lo, o->r_hi, t->split_rule);
     double mp = (o->p_lo + o->p_hi) * 0.5;
+    double am[2], alo[2], ahi[2];
+    ang_mid(o->depth, o->a_lo, o->a_hi, am);
     double rlo = (dg & 2) ? mr : o->r_lo, rhi = (dg & 2) ? o->r_hi : mr;
     double plo = (dg & 1) ? mp : o->p_lo, phi = (dg & 1) ? o->p_hi : mp;
+    for (int c = 0; c < 2; ++c) {
+        alo[c] = (dg & 1) ? am[c] : o->a_lo[c];
+        ahi[c] = (dg & 1) ? o->a_hi[c] : am[c];
+    }
     int32_t depth = o->depth + 1;
-    int32_t c = new_node(t, rlo, rhi, plo, phi, depth);
+    int32_t c = new_node(t, rlo, rhi, plo, phi, alo, ahi, depth);
     if (c < 0) return -1;
     t->nodes[nid].child[dg] = c; /* re-fetch: new_node may have moved the array */
     return c;
@@ -627,12 +674,13 @@ static ora_tree *tree_alloc(const double *Y, int64_t n, int32_t max_depth, int32
     t->px = (double *)malloc(sizeof(double) * (size_t)n);
     t->py = (double *)malloc(sizeof(double) * (size_t)n);
     t->r = (double *)malloc(sizeof(double) * (size_t)n);
-    t->phi = (double *)malloc(sizeof(double) * (size_t)n);
-    if (!t->px || !t->py || !t->r || !t->phi) { ora_tree_free(t); return NULL; }
+    t->xs = (double *)malloc(sizeof(double) * (size_t)n);
+    t->ys = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!t->px || !t->py || !t->r || !t->xs || !t->ys) { ora_tree_free(t); return NULL; }
     for (int64_t i = 0; i < n; ++i) {
         t->px[i] = Y[2 * i];
         t->py[i] = Y[2 * i + 1];
-        polar_of(t->px[i], t->py[i], &t->r[i], &t->phi[i]);
+        polar_of(t->px[i], t->py[i], &t->r[i], &t->xs[i], &t->ys[i]);
     }
     return t;
 }
@@ -645,7 +693,8 @@ static int32_t make_root(ora_tree *t) {
         if (t->r[i] < rmin) rmin = t->r[i];
         if (t->r[i] > rmax) rmax = t->r[i];
     }
-    return new_node(t, rmin, rmax, 0.0, 2.0 * M_PI, 0);
+    const double east[2] = {1.0, 0.0};  /* both bounds of the root: angle 0 = 2 pi */
+    return new_node(t, rmin, rmax, 0.0, 2.0 * M_PI, east, east, 0);
 }
 
 /* Hyperbolic diameter of a polar quadrilateral (Sec. 4-A).  The largest
@@ -791,11 +840,11 @@ static int partition(ora_tree *t, int32_t nid, int64_t *idx, int64_t cnt,
     o->is_leaf = 0;
     int64_t start[5] = {0, 0, 0, 0, 0};
     for (int64_t a = 0; a < cnt; ++a)
-        start[digit_of(t, &t->nodes[nid], t->r[idx[a]], t->phi[idx[a]]) + 1]++;
+        start[digit_of(t, &t->nodes[nid], idx[a]) + 1]++;
     for (int c = 0; c < 4; ++c) start[c + 1] += start[c];
     int64_t fill[4] = {start[0], start[1], start[2], start[3]};
     for (int64_t a = 0; a < cnt; ++a) {
-        int dg = digit_of(t, &t->nodes[nid], t->r[idx[a]], t->phi[idx[a]]);
+        int dg = digit_of(t, &t->nodes[nid], idx[a]);
         tmp[fill[dg]++] = idx[a];
     }
     memcpy(idx, tmp, sizeof(int64_t) * (size_t)cnt);
@@ -839,7 +888,7 @@ void ora_tree_free(ora_tree *t) {
     if (!t) return;
     for (int64_t k = 0; k < t->nn; ++k) free(t->nodes[k].pts);
     free(t->nodes);
-    free(t->px); free(t->py); free(t->r); free(t->phi);
+    free(t->px); free(t->py); free(t->r); free(t->xs); free(t->ys);
     free(t->pre); free(t->pre_first); free(t->pre_next);
     free(t->perm); free(t->mid); free(t->rcell);
     free(t->ecent); free(t->ediam);
@@ -924,6 +973,52 @@ static void bh_visit(bh_state *s, int32_t nid) {
     }
     for (int c = 0; c < 4; ++c)
         if (o->child[c] >= 0) bh_visit(s, o->child[c]);
+}
+
+/* Barnes-Hut gradient rows for a subset of the queries, with Z given (the
+ * sum over all queries, which the subset cannot form): the same traversal
+ * per query as ora_gradient_bh.  counters as there, summed over the subset. */
+int ora_gradient_bh_rows(const double *Y, int64_t n, const int64_t *row_ptr,
+                         const int32_t *col, const double *val, double exaggeration,
+                         const ora_tree *t, double theta, const int64_t *rows,
+                         int64_t nrows, double z, double *grad_rows, int64_t *counters) {
+    if (n < 2 || !t || t->n != n || !(theta >= 0.0) || isinf(theta) || !(z > 0.0)) return -1;
+    int64_t m = t->nn;
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *cnt = (int64_t *)calloc((size_t)(4 * (nrows > 0 ? nrows : 1)), sizeof(int64_t));
+    if (!pos || !cnt) { free(pos); free(cnt); return -2; }
+    for (int64_t k = 0; k < m; ++k) pos[t->pre[k]] = k;
+    for (int64_t r = 0; r < nrows; ++r)
+        if (rows[r] < 0 || rows[r] >= n) { free(pos); free(cnt); return -1; }
+#pragma omp parallel for num_threads(NTH()) schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t i = rows[r];
+        bh_state s;
+        memset(&s, 0, sizeof(s));
+        s.t = t;
+        s.pos_of_node = pos;
+        s.theta = theta;
+        s.i = i;
+        s.yx = Y[2 * i];
+        s.yy = Y[2 * i + 1];
+        bh_visit(&s, 0);
+        double fa[2];
+        attract_row(Y, row_ptr, col, val, i, fa);
+        grad_rows[2 * r] = 4.0 * (exaggeration * fa[0] - s.fx / z);
+        grad_rows[2 * r + 1] = 4.0 * (exaggeration * fa[1] - s.fy / z);
+        cnt[4 * r] = s.tests;
+        cnt[4 * r + 1] = s.accepts;
+        cnt[4 * r + 2] = s.pairs;
+        cnt[4 * r + 3] = s.covered;
+    }
+    if (counters) {
+        counters[0] = counters[1] = counters[2] = counters[3] = 0;
+        for (int64_t r = 0; r < nrows; ++r)
+            for (int a = 0; a < 4; ++a) counters[a] += cnt[4 * r + a];
+    }
+    free(pos);
+    free(cnt);
+    return 0;
 }
 
 int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,

@@ -94,6 +94,12 @@ int ora_gradient_bh(const double *Y, int64_t n, const int64_t *row_ptr,
  * accounted for (N_cell per accepted cell plus 1 per leaf pair); every query
  * meets each other point exactly once, so the last one equals n (n - 1). */
 
+/* the same gradient for the query rows rows[0..nrows) only, with Z given */
+int ora_gradient_bh_rows(const double *Y, int64_t n, const int64_t *row_ptr,
+                         const int32_t *col, const double *val, double exaggeration,
+                         const ora_tree *t, double theta, const int64_t *rows,
+                         int64_t nrows, double z, double *grad_rows, int64_t *counters);
+
 /* ---- h-SNE (Sec. 4-C): the Euclidean Student-t term of the disk coordinates ----
  * cost KL(P || Q^E) with q^E_ij proportional to (1 + |y_i - y_j|^2)^-1; its
  * exact gradient; and the same accelerated over the polar quadtree with

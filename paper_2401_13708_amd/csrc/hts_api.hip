@@ -189,7 +189,6 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
         {(void **)&t->pjob, nm * 4},
         {(void **)&t->root, 2 * 8},
         {(void **)&t->r, nm * 8},
-        {(void **)&t->phi, nm * 8},
         {(void **)&t->mm, (size_t)t->nb * 32},
         {(void **)&t->keys_in, nm * 8},
         {(void **)&t->keys, nm * 8},
@@ -244,7 +243,7 @@ hts_status hts_tree_destroy(hts_tree t) {
     if (!t) return fail(HTS_EINVAL, "hts_tree_destroy: tree is NULL");
     hipSetDevice(t->ctx->device);
     hipDeviceSynchronize();
-    void *ptrs[] = {t->job_off, t->job_qb, t->qb_job, t->pjob, t->root, t->r, t->phi, t->mm,
+    void *ptrs[] = {t->job_off, t->job_qb, t->qb_job, t->pjob, t->root, t->r, t->mm,
                     t->keys_in, t->keys, t->idx_in, t->perm, t->sort_tmp, t->ncnt_part,
                     t->q_part, t->node_start, t->psum, t->d_m, t->spts, t->nodes, t->r_cell,
                     t->node_first, t->sinhalf, t->enodes, t->epsum, t->epart};

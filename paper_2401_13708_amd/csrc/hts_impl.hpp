@@ -125,7 +125,7 @@ struct hts_tree_s {
     int32_t *pjob = nullptr;      // [n_max] job of each point
     int64_t nqb = 0;              // query blocks of the layout
     double *root = nullptr;       // [2J] (r_min, r_max) per job
-    double *r = nullptr, *phi = nullptr;
+    double *r = nullptr;           // [n_max] radius of every point
     double *mm = nullptr;     // per block: (min, max) of its first and of its last job
     uint64_t *keys_in = nullptr, *keys = nullptr;
     uint32_t *idx_in = nullptr, *perm = nullptr;

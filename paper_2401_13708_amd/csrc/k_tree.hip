@@ -7,8 +7,9 @@
 //     block partials), then the key of every point: max_depth levels of the
 //     split rule, two bits per
 //     level (radial bit: r at or above the radial split of eq. (10), or of
-//     eq. (9) when the tree is set to equal areas; angular bit:
-//     phi >= (lo + hi) / 2), most significant level first;
+//     eq. (9) when the tree is set to equal areas; angular bit: the point on
+//     or counter-clockwise of the cell's split ray, an exact sign test),
+//     most significant level first;
 //  3. stable radix sort of (key, index) (k_sort.hip);
 //  4. per sorted position: how many nodes start there (from the common
 //     prefixes with both neighbours), the sorted point record and the
@@ -32,18 +33,17 @@
 
 namespace hts {
 
-constexpr double kTwoPi = 2.0 * 3.14159265358979323846;
 
 // ---------------------------------------------------------------- 1. polar
-// Polar position of every point, and the radial range of every job: a job
-// that lies inside one block is reduced here completely; for the others the
-// block leaves the (min, max) of its first and of its last job's points in mm
+// Radius of every point, and the radial range of every job: a job that lies
+// inside one block is reduced here completely; for the others the block
+// leaves the (min, max) of its first and of its last job's points in mm
 // (segmented scan over the block, jobs being contiguous).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_polar(const T *__restrict__ Y, int64_t n,
                                                   const int32_t *__restrict__ pjob,
                                                   const int64_t *__restrict__ job_off,
-                                                  double *__restrict__ r, double *__restrict__ phi,
+                                                  double *__restrict__ r,
                                                   double *__restrict__ mm,
                                                   double *__restrict__ root) {
     __shared__ double smin[kBlock], smax[kBlock];
@@ -54,13 +54,10 @@ __global__ __launch_bounds__(kBlock) void k_polar(const T *__restrict__ Y, int64
     double vmin = __builtin_inf(), vmax = -__builtin_inf();
     int job = -1;
     if (i < n) {
-        // position of the single-precision coordinates; products are exact
+        // radius of the single-precision coordinates; products are exact
         double x = (double)(float)Y[2 * i], y = (double)(float)Y[2 * i + 1];
         double rr = __dsqrt_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)));
-        double p = atan2(y, x);
-        if (p < 0.0) p = __dadd_rn(p, kTwoPi);
         r[i] = rr;
-        phi[i] = p;
         vmin = vmax = rr;
         job = pjob[i];
     }
@@ -134,15 +131,49 @@ __device__ __forceinline__ double radial_mid(double lo, double hi, int rule) {
     return __dsqrt_rn(__ddiv_rn(s, __dadd_rn(2.0, s)));
 }
 
+// Angular split of a cell (Sec. 2-D: the angular range halved at
+// (max_phi + min_phi) / 2), decided without the angle of the point, whose
+// last bit would depend on the math library: the split ray is a direction
+// built from those of the cell's bounds -- the negative x-axis at the root
+// (the ray at pi), the lower bound turned by a right angle at depth 1 (widths
+// pi), below that the normalised sum of the two bound directions, every
+// operation rounded on its own in double -- and the point (x, y) is in the
+// upper half iff c y - s x >= 0, (c, s) the ray rounded to single precision.
+// With single-precision coordinates both products are exact in double and
+// the one rounding of the difference keeps its sign: the decision is exact,
+// and a point on the ray goes to the upper half.  At the root the upper half
+// is y < 0, or y = 0 and x < 0.
+__device__ __forceinline__ void ang_mid(int depth, const double *lo, const double *hi, double *mid) {
+    if (depth == 0) {
+        mid[0] = -1.0;
+        mid[1] = 0.0;
+    } else if (depth == 1) {
+        mid[0] = -lo[1];
+        mid[1] = lo[0];
+    } else {
+        const double sx = __dadd_rn(lo[0], hi[0]), sy = __dadd_rn(lo[1], hi[1]);
+        const double h = __dsqrt_rn(__dadd_rn(__dmul_rn(sx, sx), __dmul_rn(sy, sy)));
+        mid[0] = __ddiv_rn(sx, h);
+        mid[1] = __ddiv_rn(sy, h);
+    }
+}
+
+__device__ __forceinline__ int ang_bit(int depth, const double *mid, double xs, double ys) {
+    if (depth == 0) return ys < 0.0 || (ys == 0.0 && xs < 0.0);
+    const double c = (double)__double2float_rn(mid[0]), s = (double)__double2float_rn(mid[1]);
+    return __dsub_rn(__dmul_rn(c, ys), __dmul_rn(s, xs)) >= 0.0;
+}
+
 // ---------------------------------------------------------------- 2. keys
 // job index above max_depth levels of the split rule, two bits per level
-// (radial bit: r at or above the radial split; angular bit:
-// phi >= (lo + hi) / 2).  A job inside one block has its root annulus from
+// (radial bit: r at or above the radial split; angular bit: the upper half
+// of the angular split above).  A job inside one block has its root annulus from
 // k_polar; the block's first and last jobs may span other blocks, and their
 // annuli are reduced here from k_polar's partials (the block holding a job's
 // first point stores it for the later kernels).
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
-                                                 const double *__restrict__ phi, int64_t n,
+                                                 const T *__restrict__ Y, int64_t n,
                                                  const int32_t *__restrict__ pjob,
                                                  const int64_t *__restrict__ job_off,
                                                  const double *__restrict__ mm,
@@ -183,16 +214,20 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
         lo = s_range[w][0];
         hi = s_range[w][1];
     }
-    double rv = r[i], pv = phi[i];
-    double plo = 0.0, phh = kTwoPi;
+    const double rv = r[i];
+    const double xs = (double)(float)Y[2 * i], ys = (double)(float)Y[2 * i + 1];
+    double alo[2] = {1.0, 0.0}, ahi[2] = {1.0, 0.0};  // the root's bounds: angle 0 = 2 pi
     uint64_t key = (uint64_t)job;
     for (int l = 0; l < L; ++l) {
-        double mr = radial_mid(lo, hi, split);
-        double mp = __dmul_rn(__dadd_rn(plo, phh), 0.5);
-        int rb = rv >= mr, pb = pv >= mp;
+        const double mr = radial_mid(lo, hi, split);
+        double am[2];
+        ang_mid(l, alo, ahi, am);
+        const int rb = rv >= mr, pb = ang_bit(l, am, xs, ys);
         key = (key << 2) | (uint64_t)(2 * rb + pb);
         if (rb) lo = mr; else hi = mr;
-        if (pb) plo = mp; else phh = mp;
+        double *bound = pb ? alo : ahi;
+        bound[0] = am[0];
+        bound[1] = am[1];
     }
     keys[i] = key;
     idx[i] = (uint32_t)i;
@@ -523,9 +558,9 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     const int L = t->max_depth;
     const int64_t nb = cdiv(n, kBlock);
     hipLaunchKernelGGL(k_polar<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->pjob, t->job_off, t->r,
-                       t->phi, t->mm, t->root);
+                       t->mm, t->root);
     HTS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(kBlock), 0, st, t->r, t->phi, n, t->pjob, t->job_off,
+    hipLaunchKernelGGL(k_keys<T>, dim3(nb), dim3(kBlock), 0, st, t->r, Y, n, t->pjob, t->job_off,
                        t->mm, t->root, L, t->split_rule, t->keys_in, t->idx_in);
     HTS_HIP(hipGetLastError());
     HTS_OKR(radix_sort_pairs(st, t->keys_in, t->idx_in, t->keys, t->perm, n, 2 * L + t->job_bits,

@@ -22,6 +22,11 @@ is reproduced here):
   states an optimisation passes through; used as shared parity inputs.
 * ``random_csr``         -- a sparse row structure with the row lengths of a
   symmetrised k-NN graph, for timing-only inputs.
+* ``near_split_rays``    -- adversarial tree inputs: single-precision points a
+  few units in the last place either side of the rays that halve the angular
+  range of the polar quadtree's cells (angles 2 pi (2j + 1) / 2^(l + 1) at
+  level l), where an angle computed by a math library could fall on either
+  side.
 """
 from __future__ import annotations
 
@@ -36,6 +41,7 @@ __all__ = [
     "disk_state",
     "random_csr",
     "subsample",
+    "near_split_rays",
 ]
 
 
@@ -156,3 +162,35 @@ def subsample(n: int, m: int, seed: int = 99) -> np.ndarray:
     """Sorted uniform sample of m distinct row indices out of n."""
     g = rng(seed)
     return np.sort(g.choice(n, size=min(m, n), replace=False)).astype(np.int64)
+
+
+def near_split_rays(levels=range(1, 20), rays_per_level: int = 3, ulps=(-2, -1, 0, 1, 2),
+                    seed: int = 61, background: int = 300) -> np.ndarray:
+    """Single-precision points straddling the angular split rays.
+
+    For every level l and a few random cells j of that level, the ray at
+    angle 2 pi (2j + 1) / 2^(l + 1) (the middle of the cell's angular range)
+    gets a point at a random radius rounded to single precision, and copies
+    of it moved by the given numbers of units in the last place along x;
+    such a family shares every cell above level l and is split by the ray.
+    A uniform background keeps the root annulus and the upper levels busy."""
+    g = rng(seed)
+    pts = []
+    for lvl in levels:
+        for _ in range(rays_per_level):
+            j = int(g.integers(0, 2 ** lvl))
+            a = 2.0 * np.pi * (2 * j + 1) / 2.0 ** (lvl + 1)
+            r = g.uniform(0.05, 0.95)
+            x = np.float32(r * np.cos(a))
+            y = np.float32(r * np.sin(a))
+            for u in ulps:
+                xu = x
+                step = np.float32(np.inf) if u > 0 else np.float32(-np.inf)
+                for _ in range(abs(u)):
+                    xu = np.nextafter(xu, step)
+                pts.append((xu, y))
+    r = 0.95 * np.sqrt(g.random(background))
+    phi = 2.0 * np.pi * g.random(background)
+    bg = np.stack([r * np.cos(phi), r * np.sin(phi)], axis=1).astype(np.float32)
+    out = np.concatenate([np.array(pts, dtype=np.float32), bg])
+    return np.ascontiguousarray(out[g.permutation(out.shape[0])])

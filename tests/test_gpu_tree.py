@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2401_13708_amd import hts
+from paper_2401_13708_amd import hts, synth
 from gpu_inputs import STAGES, embedding
 
 pytestmark = pytest.mark.gpu
@@ -94,3 +94,16 @@ def test_tree_equal_area_duplicates_and_caps(ctx):
     Y[100:160] = Y[7]
     for depth in (20, 5):
         _compare(ctx, Y, depth, mid_rtol=1e-11, split=1)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("max_depth,split", [(20, 0), (24, 0), (20, 1)])
+def test_tree_points_straddling_the_split_rays(ctx, dtype, max_depth, split):
+    # families of points a few units in the last place either side of the
+    # rays that halve the cells' angular ranges at levels 1-19 (and 20-23
+    # for the deeper cap): the angular decision is an exact sign test on both
+    # sides, so the trees agree node for node even there
+    levels = range(1, min(max_depth, 24))
+    Y = synth.near_split_rays(levels=levels, seed=61 + max_depth).astype(dtype)
+    # midpoints of the single-precision tree are stored in single precision
+    _compare(ctx, Y, max_depth, mid_rtol=1.2e-7 if dtype == np.float32 else 1e-11, split=split)

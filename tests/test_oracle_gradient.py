@@ -296,3 +296,21 @@ def test_bh_accounts_for_every_point_once_with_duplicates_and_depth_cap():
         t = oracle.Tree(Y, max_depth=depth)
         _, _, cnt = oracle.gradient_bh(Y, rp, col, val, t, 0.5, 1.0)
         assert cnt["covered"] == n * (n - 1)
+
+
+@pytest.mark.parametrize("stage,theta", [("mid", 0.5), ("edge", 0.3), ("early", 0.0)])
+def test_bh_rows_equal_the_whole_bh_gradient(stage, theta):
+    # the row-subset traversal (used to time a bounded sample of queries)
+    # gives each sampled row of the whole Barnes-Hut gradient, and its
+    # counters are those rows' share
+    Y, rp, col, val = _problem(70, seed=41, stage=stage)
+    t = oracle.Tree(Y)
+    g, z, cnt = oracle.gradient_bh(Y, rp, col, val, t, theta, 12.0)
+    rows = np.arange(Y.shape[0])
+    gr, cr = oracle.gradient_bh_rows(Y, rp, col, val, t, theta, rows, z, 12.0)
+    assert np.array_equal(gr, g)
+    assert cr == cnt
+    sub = synth.rng(42).permutation(Y.shape[0])[:9]
+    gs, cs = oracle.gradient_bh_rows(Y, rp, col, val, t, theta, sub, z, 12.0)
+    assert np.array_equal(gs, g[sub])
+    assert cs["covered"] == 9 * (Y.shape[0] - 1)

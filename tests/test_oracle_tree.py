@@ -262,3 +262,70 @@ def test_equal_area_small_tree_matches_brute_force():
     want = [(len(k), nodes[k]) for k in sorted(nodes)]
     e = oracle.Tree(Y, depth, split_rule=1).export()
     assert list(zip(e["depth"].tolist(), e["count"].tolist())) == want
+
+
+# ---------------------------------------------------------------- angular split
+def test_sign_of_the_split_test_is_exact():
+    # the angular decision is the sign of c y - s x with single-precision c,
+    # s, x, y evaluated in double: both products are exact (48 significant
+    # bits) and one rounding cannot change the sign of the difference.
+    # Checked against rational arithmetic on points within a few units in
+    # the last place of the ray (c, s).
+    from fractions import Fraction
+    g = synth.rng(71)
+    bad = 0
+    for _ in range(4000):
+        a = g.uniform(0.0, 2.0 * np.pi)
+        c, s = np.float32(np.cos(a)), np.float32(np.sin(a))
+        r = g.uniform(1e-4, 0.999)
+        x, y = np.float32(r * np.cos(a)), np.float32(r * np.sin(a))
+        for _ in range(int(g.integers(0, 4))):
+            x = np.nextafter(x, np.float32(g.choice([-1.0, 1.0])))
+        fast = float(c) * float(y) - float(s) * float(x)
+        exact = Fraction(float(c)) * Fraction(float(y)) - Fraction(float(s)) * Fraction(float(x))
+        bad += (fast >= 0.0) != (exact >= 0)
+        bad += (fast == 0.0) != (exact == 0)
+    assert bad == 0
+
+
+def _leaf_bounds_of_points(e):
+    # bounds of the leaf holding each point (a leaf is a node with next = k + 1)
+    m = e["count"].size
+    out = {}
+    for k in range(m):
+        if e["next"][k] == k + 1:
+            for a in range(e["first"][k], e["first"][k] + e["count"][k]):
+                out[int(e["perm"][a])] = e["bounds"][k]
+    return out
+
+
+def test_points_on_split_rays_go_to_the_upper_half():
+    # points exactly on the rays at multiples of pi/4 (coordinates exactly
+    # representable, x = +-y on the diagonals): the tree sends a point on a
+    # cell's split ray to the upper half, as phi >= (min + max) / 2 does, so
+    # the leaf holding a point at angle phi has p_lo <= phi < p_hi
+    rad = np.array([0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8], dtype=np.float64)
+    dirs = [(1, 0), (1, 1), (0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1)]
+    Y = np.array([(r * dx, r * dy) for dx, dy in dirs for r in rad])
+    phis = np.array([k * np.pi / 4 for k in range(8) for _ in rad])
+    for depth in (6, 20):
+        e = oracle.Tree(Y, depth).export()
+        lb = _leaf_bounds_of_points(e)
+        for i in range(Y.shape[0]):
+            plo, phi = lb[i][2], lb[i][3]
+            assert plo <= phis[i] + 1e-15 and phis[i] < phi - 1e-15, (i, phis[i], plo, phi)
+
+
+def test_near_ray_points_insertion_equals_partition_and_brute_force_away_from_rays():
+    Y = synth.near_split_rays().astype(np.float64)
+    a = oracle.Tree(Y, L, "insert").export()
+    b = oracle.Tree(Y, L, "partition").export()
+    for key in ("count", "depth", "first", "next", "perm"):
+        assert np.array_equal(a[key], b[key]), key
+    # every point lies in its leaf's angular range up to the rounding of the
+    # split rays (a few 1e-8 rad)
+    r, p = _polar32(Y)
+    lb = _leaf_bounds_of_points(a)
+    for i in range(Y.shape[0]):
+        plo, phi = lb[i][2], lb[i][3]
+        assert plo - 1e-7 <= p[i] <= phi + 1e-7
