@@ -91,6 +91,18 @@ class Embedding:
                     break
         return self
 
+    def snapshot(self):
+        """Device copies of the optimiser state (Y, update, gains) and the
+        iteration counter, to restart the schedule from later."""
+        return (self.Y.clone(), self.update.clone(), self.gains.clone(), self.it)
+
+    def restore(self, snap):
+        Y, U, G, it = snap
+        self.Y.copy_(Y)
+        self.update.copy_(U)
+        self.gains.copy_(G)
+        self.it = int(it)
+
     def state_dict(self) -> dict:
         return {"Y": self.Y.cpu().numpy(), "update": self.update.cpu().numpy(),
                 "gains": self.gains.cpu().numpy(), "it": self.it}

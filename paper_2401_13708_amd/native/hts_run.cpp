@@ -13,15 +13,23 @@
 // usage: hts_run --peaks     (attainable copy bandwidth and vector FMA rates)
 //        hts_run <input.bin> [--warmup W] [--steps K] [--theta T]
 //                [--item-list L] [--copy-mib M] [--out Y.bin] [--progress P]
+//                [--reload]
 //   input.bin: int64 n, int32 d, int32 it0, float X[n*d] (row-major),
 //              float Y0[2n] (the embedding in the Poincare disk at iteration
-//              it0 of the schedule, where the run starts; update 0, gains 1)
+//              it0 of the schedule, where the run starts), optionally float
+//              update[2n] and gains[2n] of the optimiser at it0 (else update
+//              0 and gains 1)
 //   Y.bin:     float Y[2n] after the warm-up and timed iterations
 //   --progress P: a line on stderr every P iterations as they are issued
 //                 (for runs under a profiler that serialises launches)
+//   --reload:     the warm-up runs the counting kernels (same results), then
+//                 the state of the input file is loaded again, so the timed
+//                 steps are iterations it0 .. it0 + K - 1 from that state and
+//                 the plain kernels run in them only (a window of bench.py)
 // Exit status 0 on success; otherwise the failing call is printed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -154,7 +162,12 @@ int main(int argc, char **argv) {
     double theta = 0.5;
     int64_t copy_mib = 0;
     const char *out_path = nullptr;
+    bool reload = false;
     for (int a = 2; a < argc; ++a) {
+        if (!std::strcmp(argv[a], "--reload")) {
+            reload = true;
+            continue;
+        }
         if (a + 1 >= argc) {
             std::fprintf(stderr, "hts_run: %s needs a value\n", argv[a]);
             return 2;
@@ -194,8 +207,14 @@ int main(int argc, char **argv) {
         return 1;
     }
     std::vector<float> X((size_t)n * d), Y0(2 * (size_t)n);
+    std::vector<float> U0(2 * (size_t)n, 0.0f), G0(2 * (size_t)n, 1.0f);
     read_all(in, X.data(), X.size());
     read_all(in, Y0.data(), Y0.size());
+    // the optimiser state, when the file carries it
+    if (std::fread(U0.data(), sizeof(float), U0.size(), in) == U0.size())
+        read_all(in, G0.data(), G0.size());
+    else
+        std::fill(U0.begin(), U0.end(), 0.0f);
     std::fclose(in);
 
     hipStream_t st;
@@ -230,36 +249,45 @@ int main(int argc, char **argv) {
     HIPCHK(hipMalloc(&dGain, sizeof(float) * 2 * n));
     HIPCHK(hipMalloc(&dG, sizeof(float) * 2 * n));
     HIPCHK(hipMalloc(&dz, sizeof(double)));
-    std::vector<float> zeros(2 * n, 0.0f), ones(2 * n, 1.0f);
-    HIPCHK(hipMemcpy(dY, Y0.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(dU, zeros.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(dGain, ones.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+    auto upload_state = [&]() {
+        HIPCHK(hipMemcpy(dY, Y0.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dU, U0.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dGain, G0.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+    };
+    upload_state();
     hts_tree tree = nullptr;
     HTSCHK(hts_tree_create(ctx, n, 20, &tree));
 
     const double eta = (double)n / 12000.0;
+    uint64_t *dstats = nullptr;  // counters of the counting kernels (not read)
+    HIPCHK(hipMalloc(&dstats, 64 * sizeof(uint64_t)));
+    HIPCHK(hipMemset(dstats, 0, 64 * sizeof(uint64_t)));
     int it = it0;
-    auto iterate = [&]() {
+    auto iterate = [&](bool counting) {
         const bool early = it < 250;
         const double ex = early ? 12.0 : 1.0, mu = early ? 0.5 : 0.8;
         HTSCHK(hts_build_polar_tree(ctx, st, dY, n, HTS_F32, tree));
         HTSCHK(hts_gradient_bh(ctx, st, dY, n, HTS_F32, drp, dcol, dval, ex, tree, theta, dG, dz,
-                               nullptr));
+                               counting ? dstats : nullptr));
         HTSCHK(hts_step(ctx, st, dY, dU, dGain, dG, n, HTS_F32, eta, mu, 0.01, 1e-5, 2));
         ++it;
         if (progress > 0 && it % progress == 0) std::fprintf(stderr, "hts_run: iteration %d issued\n", it);
     };
-    for (int w = 0; w < warmup; ++w) iterate();
     uint32_t bits = 0;
-    HTSCHK(hts_check(ctx, st, &bits));
-    std::fprintf(stderr, "hts_run: %d warm-up iterations done\n", warmup);
-
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    for (int w = 0; w < warmup; ++w) iterate(reload);
+    HTSCHK(hts_check(ctx, st, &bits));
+    if (reload) {
+        upload_state();
+        it = it0;
+    }
+    std::fprintf(stderr, "hts_run: %d warm-up iterations done%s\n", warmup,
+                 reload ? " (counting kernels; state loaded again)" : "");
     t0 = now_s();
     HIPCHK(hipEventRecord(e0, st));
-    for (int s = 0; s < steps; ++s) iterate();
+    for (int s = 0; s < steps; ++s) iterate(false);
     HIPCHK(hipEventRecord(e1, st));
     HTSCHK(hts_check(ctx, st, &bits));
     const double wall = now_s() - t0;
@@ -302,7 +330,7 @@ int main(int argc, char **argv) {
     HIPCHK(hipEventDestroy(e1));
     HIPCHK(hipStreamDestroy(st));
     for (void *p : {(void *)drp, (void *)dcol, (void *)dval, (void *)dY, (void *)dU, (void *)dGain,
-                    (void *)dG, (void *)dz})
+                    (void *)dG, (void *)dz, (void *)dstats})
         HIPCHK(hipFree(p));
     return 0;
 }

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2401_13708_amd import synth
-from gpu_inputs import embedding, rel
+from gpu_inputs import embedding, rel, rel_row
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +42,7 @@ def test_c_caller_one_iteration(tmp_path, n, stage):
     Yo = Y.astype(np.float64)
     go, zo, _ = oracle.gradient_bh(Yo, rp, col, val.astype(np.float64), oracle.Tree(Yo), theta, ex)
     assert rel(g, go) < 1e-3
+    assert rel_row(g, go) < 1e-3
     assert z == pytest.approx(zo, rel=1e-5)
     Yo1, _, _ = oracle.step(Yo, np.zeros_like(Yo), np.ones_like(Yo), go, eta, mu)
     # the step moves by eta * gains * metric * gradient: its error follows the

@@ -2,12 +2,12 @@
 library calls and launch configuration the benchmark times.
 
 * N = 70000, D = 784 single precision (the headline workload): affinities
-  (kNN rows sampled against the oracle bit-exactly, the CSR pattern and the
+  (256 kNN rows sampled against the oracle bit-exactly, the CSR pattern and the
   symmetry of P over the whole result, sampled rows of P against the oracle's
   conditional probabilities), the polar quadtree (whole tree bit-exact), the
   Barnes-Hut gradient (whole result against the oracle's Barnes-Hut), the
   exact gradient (sampled rows, with the oracle's all-pairs Z) and the step.
-* N = 200000, D = 50 (the hierarchical workload): kNN rows sampled, and the
+* N = 200000, D = 50 (the hierarchical workload): 256 kNN rows sampled, and the
   Barnes-Hut gradient at theta in {0.3, 0.5, 0.8} against the oracle.
 * N = 3.1 million (near the largest tree the 26-bit node indices allow at
   depth 20): the whole tree bit-exact; N = 1 million: the whole Barnes-Hut
@@ -21,7 +21,7 @@ import torch
 
 import oracle
 from paper_2401_13708_amd import hts, synth
-from gpu_inputs import embedding, rel
+from gpu_inputs import embedding, rel, rel_row
 from test_gpu_step import step_case
 
 pytestmark = pytest.mark.gpu
@@ -55,6 +55,14 @@ def _check_pattern_and_symmetry(knn, rp, col, val):
     assert float(np.sum(val.astype(np.float64))) == pytest.approx(1.0, abs=1e-5)
 
 
+def _check_knn_rows(X, knn, k, samples):
+    # neighbour lists of sampled rows, bit for bit (the oracle computes each
+    # row against all n points)
+    oi, _ = oracle.knn_rows(X, k, samples)
+    bad = [int(i) for r, i in enumerate(samples) if not np.array_equal(knn[i], oi[r])]
+    assert not bad, bad[:8]
+
+
 def _check_sampled_rows(X, knn, rp, col, val, perp, k, samples):
     n = X.shape[0]
     oi, od2 = oracle.knn_rows(X, k, samples)
@@ -79,16 +87,18 @@ def test_affinities_headline_size(ctx):
     X = synth.sigmoid_factor_mixture(N_HEAD, 784, seed=2)
     knn, rp, col, val = _affinities(ctx, X, 30.0, 90)
     _check_pattern_and_symmetry(knn, rp, col, val)
-    _check_sampled_rows(X.astype(np.float64), knn, rp, col, val, 30.0, 90,
-                        synth.subsample(N_HEAD, 3, seed=21))
+    X64 = X.astype(np.float64)
+    _check_knn_rows(X64, knn, 90, synth.subsample(N_HEAD, 256, seed=20))
+    _check_sampled_rows(X64, knn, rp, col, val, 30.0, 90, synth.subsample(N_HEAD, 3, seed=21))
 
 
 def test_affinities_hierarchical_size(ctx):
     X = synth.branching_walk(N_HIER, 50, seed=3).astype(np.float32)
     knn, rp, col, val = _affinities(ctx, X, 30.0, 90)
     _check_pattern_and_symmetry(knn, rp, col, val)
-    _check_sampled_rows(X.astype(np.float64), knn, rp, col, val, 30.0, 90,
-                        synth.subsample(N_HIER, 3, seed=31))
+    X64 = X.astype(np.float64)
+    _check_knn_rows(X64, knn, 90, synth.subsample(N_HIER, 256, seed=30))
+    _check_sampled_rows(X64, knn, rp, col, val, 30.0, 90, synth.subsample(N_HIER, 3, seed=31))
 
 
 @pytest.mark.parametrize("stage", ["init", "mid", "edge"])
@@ -128,6 +138,8 @@ def _bh_against_oracle(ctx, n, stage, theta, ex, csr_seed):
     Yo = Y.astype(np.float64)
     go, zo, cnt = oracle.gradient_bh(Yo, rp, col, v32.astype(np.float64), oracle.Tree(Yo), theta, ex)
     assert rel(g, go) < 1e-3
+    print("rel_row %.2e" % rel_row(g, go))
+    assert rel_row(g, go) < 1e-3
     assert z == pytest.approx(zo, rel=1e-5)
     # single-precision midpoints may flip criterion decisions that the double
     # oracle takes within rounding of the threshold: a few per million
@@ -180,6 +192,8 @@ def test_bh_million_points(ctx):
     Yo = Y.astype(np.float64)
     go, zo, _ = oracle.gradient_bh(Yo, rp, col, v32.astype(np.float64), oracle.Tree(Yo), 0.5, 12.0)
     assert rel(g, go) < 1e-3
+    print("rel_row %.2e" % rel_row(g, go))
+    assert rel_row(g, go) < 1e-3
     assert z == pytest.approx(zo, rel=1e-5)
 
 
@@ -197,6 +211,7 @@ def test_exact_headline_size_sampled_rows(ctx):
     rows = synth.subsample(N_HEAD, 512, seed=22)
     go = oracle.gradient_exact_rows(Yo, rp, col, v32.astype(np.float64), rows, zo, 12.0)
     assert rel(g[rows], go) < 1e-4
+    assert rel_row(g[rows], go) < 1e-4
 
 
 def test_bh_error_against_exact_grows_with_theta(ctx):

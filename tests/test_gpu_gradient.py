@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_2401_13708_amd import hts, synth
-from gpu_inputs import STAGES, affinities, embedding, rel
+from gpu_inputs import STAGES, affinities, embedding, rel, rel_row
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +65,7 @@ def test_exact_f32(ctx, stage, n):
     g, z = _run_exact(ctx, Y, rp, col, v32, 12.0)
     go, zo = oracle.gradient_exact(Y.astype(np.float64), rp, col, v32.astype(np.float64), 12.0)
     assert rel(g, go) < 1e-4
+    assert rel_row(g, go) < 1e-4
     assert z == pytest.approx(zo, rel=1e-5)
 
 
@@ -178,6 +179,8 @@ def test_bh_f32_matches_oracle_bh(ctx, stage, theta):
     t = oracle.Tree(Yo)
     go, zo, _ = oracle.gradient_bh(Yo, rp, col, v32.astype(np.float64), t, theta, 12.0)
     assert rel(g, go) < 1e-3
+    print("rel_row %.2e" % rel_row(g, go))
+    assert rel_row(g, go) < 1e-3
     assert z == pytest.approx(zo, rel=1e-5)
 
 

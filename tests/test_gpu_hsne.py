@@ -14,7 +14,7 @@ import torch
 
 import oracle
 from paper_2401_13708_amd import hts, synth
-from gpu_inputs import STAGES, affinities, embedding, rel
+from gpu_inputs import STAGES, affinities, embedding, rel, rel_row
 
 pytestmark = pytest.mark.gpu
 
@@ -74,6 +74,8 @@ def test_hsne_f32_matches_oracle(ctx, stage, theta):
     g, z = _run(ctx, Y, rp, col, v32, 12.0, 1.5, theta)
     go, ze, zh, _, _ = _oracle(Y, rp, col, v32, 12.0, 1.5, theta)
     assert rel(g, go) < 1e-3
+    print("rel_row %.2e" % rel_row(g, go))
+    assert rel_row(g, go) < 1e-3
     assert z[0] == pytest.approx(ze, rel=1e-5)
     assert z[1] == pytest.approx(zh, rel=1e-5)
 
@@ -194,6 +196,8 @@ def test_hsne_headline_size(ctx, stage):
     g, z = _run(ctx, Y, rp, col, v32, 12.0, 1.0, 0.5)
     go, ze, zh, _, _ = _oracle(Y, rp, col, v32, 12.0, 1.0, 0.5)
     assert rel(g, go) < 1e-3
+    print("rel_row %.2e" % rel_row(g, go))
+    assert rel_row(g, go) < 1e-3
     assert z[0] == pytest.approx(ze, rel=1e-5)
     assert z[1] == pytest.approx(zh, rel=1e-5)
 

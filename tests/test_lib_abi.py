@@ -76,7 +76,8 @@ def test_item_list_share_needs_a_context():
 
 def test_native_driver_input_file(tmp_path):
     # bench.py writes the native driver's input: header (n, d, start
-    # iteration) and the same seeded X and starting embedding the bench uses
+    # iteration), the same seeded X and starting embedding the bench uses, and
+    # the optimiser state
     import numpy as np
     from paper_2401_13708_amd import synth
     path = tmp_path / "in.bin"
@@ -87,11 +88,12 @@ def test_native_driver_input_file(tmp_path):
     raw = path.read_bytes()
     assert np.frombuffer(raw[:8], np.int64)[0] == 300
     assert np.frombuffer(raw[8:16], np.int32).tolist() == [5, 0]
-    assert len(raw) == 16 + 4 * 300 * 5 + 4 * 300 * 2
+    assert len(raw) == 16 + 4 * 300 * 5 + 3 * 4 * 300 * 2
     X = np.frombuffer(raw[16:16 + 4 * 1500], np.float32).reshape(300, 5)
-    Y = np.frombuffer(raw[16 + 4 * 1500:], np.float32).reshape(300, 2)
+    Y, U, G = np.frombuffer(raw[16 + 4 * 1500:], np.float32).reshape(3, 300, 2)
     assert np.array_equal(X, synth.sigmoid_factor_mixture(300, 5, seed=2).astype(np.float32))
     assert np.array_equal(Y, synth.disk_uniform(300, 1e-4, seed=2 + 10 ** 6).astype(np.float32))
+    assert not U.any() and (G == 1).all()   # the optimiser's start: update 0, gains 1
 
 
 def test_native_driver_is_built_for_gfx950():
