@@ -106,7 +106,9 @@ hts_status hts_build_affinities(hts_ctx ctx, hts_stream stream, const void *X,
  * ---------------------------------------------------------------------- */
 
 /* Tree storage for up to n_max points; max_depth in [1, 24] (20 is the
- * default of the tree readings).  Allocates device memory once. */
+ * default of the tree readings).  Allocates device memory once.  A tree may
+ * be destroyed after its context (hts_tree_destroy is then the only valid
+ * call on it). */
 hts_status hts_tree_create(hts_ctx ctx, int64_t n_max, int32_t max_depth,
                            hts_tree *out);
 hts_status hts_tree_destroy(hts_tree tree);

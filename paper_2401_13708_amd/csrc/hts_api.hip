@@ -176,6 +176,7 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
     HTS_HIP(hipSetDevice(c->device));
     hts_tree t = new hts_tree_s();
     t->ctx = c;
+    t->device = c->device;
     t->n_max = n_max;
     t->max_depth = max_depth;
     t->cap_nodes = cap;
@@ -241,7 +242,7 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
 
 hts_status hts_tree_destroy(hts_tree t) {
     if (!t) return fail(HTS_EINVAL, "hts_tree_destroy: tree is NULL");
-    hipSetDevice(t->ctx->device);
+    hipSetDevice(t->device);  // not through ctx, which may be destroyed already
     hipDeviceSynchronize();
     void *ptrs[] = {t->job_off, t->job_qb, t->qb_job, t->pjob, t->root, t->r, t->mm,
                     t->keys_in, t->keys, t->idx_in, t->perm, t->sort_tmp, t->ncnt_part,

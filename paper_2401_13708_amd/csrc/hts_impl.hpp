@@ -107,6 +107,7 @@ struct hts_ctx_s {
 
 struct hts_tree_s {
     hts_ctx ctx = nullptr;
+    int device = 0;           // the context's device (the tree may outlive the context)
     int64_t n_max = 0;
     int32_t max_depth = 20;
     int64_t cap_nodes = 0;

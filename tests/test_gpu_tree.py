@@ -22,8 +22,9 @@ def _gpu_tree(ctx, Y, max_depth=20, split=0):
     return out
 
 
-def _compare(ctx, Y, max_depth=20, mid_rtol=1e-12, split=0):
-    g = _gpu_tree(ctx, Y, max_depth, split)
+def _compare(ctx, Y, max_depth=20, mid_rtol=1e-12, split=0, g=None):
+    if g is None:
+        g = _gpu_tree(ctx, Y, max_depth, split)
     o = oracle.Tree(Y.astype(np.float64), max_depth, split_rule=split).export()
     assert g["count"].size == o["count"].size
     for key in ("count", "depth", "first", "next"):
@@ -107,3 +108,48 @@ def test_tree_points_straddling_the_split_rays(ctx, dtype, max_depth, split):
     Y = synth.near_split_rays(levels=levels, seed=61 + max_depth).astype(dtype)
     # midpoints of the single-precision tree are stored in single precision
     _compare(ctx, Y, max_depth, mid_rtol=1.2e-7 if dtype == np.float32 else 1e-11, split=split)
+
+
+def test_tree_destroyed_after_its_context():
+    # destroying a tree after its context touches nothing of the context, and
+    # leaves no HIP error behind for the next call
+    c = hts.Context(0)
+    t = hts.Tree(c, 1000, 20)
+    hts.build_polar_tree(c, torch.from_numpy(embedding(1000, "mid", np.float32)).cuda(), t)
+    torch.cuda.synchronize()
+    c.close()
+    t.close()
+    c2 = hts.Context(0)
+    Y = torch.from_numpy(embedding(300, "mid", np.float32)).cuda()
+    t2 = hts.Tree(c2, 300, 20)
+    hts.build_polar_tree(c2, Y, t2)
+    torch.cuda.synchronize()
+    assert c2.check() == 0
+    t2.close()
+    c2.close()
+
+
+def test_tree_build_replayed_from_a_graph_on_new_points(ctx):
+    # a tree build captured as a HIP graph and replayed on other points of
+    # the same size gives their tree: every buffer the build reads is written
+    # earlier in the same build, so no replay depends on what an earlier one
+    # left (40 sort tiles, 5 digit passes, other GPU work between the replays)
+    n = 20000
+    t = hts.Tree(ctx, n, 20)
+    Ybuf = torch.from_numpy(embedding(n, "mid", np.float32)).cuda()
+    hts.build_polar_tree(ctx, Ybuf, t)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        hts.build_polar_tree(ctx, Ybuf, t)
+    scratch = torch.ones(1 << 20, device="cuda")
+    for k, stage in enumerate(STAGES + STAGES[::-1]):
+        Y = embedding(n, stage, np.float32, seed=200 + k)
+        Ybuf.copy_(torch.from_numpy(Y))
+        g.replay()
+        scratch.mul_(1.0001)
+        torch.cuda.synchronize()
+        print("replay", k, stage, flush=True)
+        _compare(ctx, Y, mid_rtol=1.2e-7, g=hts.tree_export(ctx, t, n))
+    assert ctx.check() == 0
+    t.close()
