@@ -4,7 +4,10 @@
 //  1. exact k-NN: a block owns 64 queries and streams every candidate in
 //     tiles of 128; each thread accumulates a 4 x 8 block of squared
 //     distances in double precision, summing the dimensions in ascending order
-//     with one fused multiply-add per term (a fixed, reproducible order).  A
+//     with one fused multiply-add per term (a fixed, reproducible order).
+//     The dimensions come through LDS in stages of 16; each thread's share of
+//     the next stage is loaded into registers while the current one is summed
+//     (twelve loads in flight, from clamped addresses).  A
 //     running top-k list per query (ordered by distance, then index) is
 //     merged with the candidates that beat its current k-th entry by a
 //     one-wave bitonic sort in LDS; after the first tiles almost no
@@ -79,6 +82,26 @@ __global__ __launch_bounds__(kBlock) void k_knn(const XT *__restrict__ X, int64_
     }
     __syncthreads();
 
+    // the thread's share of a stage: dimension kk of 4 queries and 8
+    // candidates, loaded from clamped (always valid) addresses so that all
+    // twelve loads are in flight at once; entries outside the data are zeroed
+    // when they are stored to LDS
+    const int kk = tid & 15;
+    XT qr[4], cr[8];
+    auto load_stage = [&](int64_t c0, int k0) {
+        const int64_t dim = k0 + kk < d ? k0 + kk : d - 1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t q = q0 + (tid >> 4) + 16 * r;
+            qr[r] = X[(q < n ? q : n - 1) * d + dim];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t c = c0 + (tid >> 4) + 16 * r;
+            cr[r] = X[(c < n ? c : n - 1) * d + dim];
+        }
+    };
+    load_stage(0, 0);
     for (int64_t c0 = 0; c0 < n; c0 += kC) {
         double acc[4][8];
 #pragma unroll
@@ -86,21 +109,22 @@ __global__ __launch_bounds__(kBlock) void k_knn(const XT *__restrict__ X, int64_
 #pragma unroll
             for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
         for (int k0 = 0; k0 < d; k0 += kD) {
-            const int kk = tid & 15;
             const bool din = k0 + kk < d;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int qq = (tid >> 4) + 16 * r;
-                int64_t q = q0 + qq;
-                Qs[kk][qq] = (q < n && din) ? (double)X[q * d + k0 + kk] : 0.0;
+                Qs[kk][qq] = (q0 + qq < n && din) ? (double)qr[r] : 0.0;
             }
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 int cc = (tid >> 4) + 16 * r;
-                int64_t c = c0 + cc;
-                Cs[kk][cc] = (c < n && din) ? (double)X[c * d + k0 + kk] : 0.0;
+                Cs[kk][cc] = (c0 + cc < n && din) ? (double)cr[r] : 0.0;
             }
             __syncthreads();
+            // the next stage (of this tile, else the next tile's first) is
+            // loaded while this one is summed
+            if (k0 + kD < d) load_stage(c0, k0 + kD);
+            else if (c0 + kC < n) load_stage(c0 + kC, 0);
             const int kmax = d - k0 < kD ? d - k0 : kD;
             for (int s = 0; s < kmax; ++s) {
                 double qv[4], cv[8];
@@ -121,6 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_knn(const XT *__restrict__ X, int64_
         // merge the tile into the running lists of this wave's 16 queries
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
+            // one query at a time (not unrolled: the merge's registers then
+            // fit two waves per SIMD beside the distance tile)
+#pragma unroll 1
             for (int r = 0; r < 4; ++r) {
                 const int qq = 4 * w + r + 16 * a;
                 const int64_t q = q0 + qq;
