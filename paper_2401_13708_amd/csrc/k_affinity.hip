@@ -15,10 +15,12 @@
 //  2. bandwidth per row: 100 bisection steps on beta = 1 / (2 sigma^2) so the
 //     entropy of p_{j|i} equals ln(perplexity); one wave per row.
 //  3. P = (P_c + P_c^T) / (2 n): both orientations of every (i, j, p_{j|i})
-//     are sorted by (row, col), duplicates summed, and written as CSR.
+//     are sorted by (row, col) with the library's radix sort (keys with
+//     their positions; the values follow by a gather), duplicates summed
+//     (each appears at most twice: a + b = b + a, so the sum does not depend
+//     on their order), and written as CSR at positions from an exclusive
+//     scan of the first-copy flags.
 #include <climits>
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include "hts_impl.hpp"
 #include "hts_math.hpp"
@@ -271,6 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_coo(const int32_t *__restrict__ lj,
                                                 const double *__restrict__ pc, int64_t n, int k,
                                                 uint64_t *__restrict__ keys,
                                                 double *__restrict__ vals,
+                                                uint32_t *__restrict__ at,
                                                 int32_t *__restrict__ knn_out) {
     int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n * k) return;
@@ -281,7 +284,88 @@ __global__ __launch_bounds__(kBlock) void k_coo(const int32_t *__restrict__ lj,
     keys[2 * e + 1] = (uint64_t)(j * n + i);
     vals[2 * e] = p;
     vals[2 * e + 1] = p;
+    at[2 * e] = (uint32_t)(2 * e);
+    at[2 * e + 1] = (uint32_t)(2 * e + 1);
     if (knn_out) knn_out[e] = (int32_t)j;
+}
+
+// the values in sorted order: vout[t] = vin[at[t]]
+__global__ __launch_bounds__(kBlock) void k_gather_vals(const uint32_t *__restrict__ at,
+                                                        const double *__restrict__ vin, int64_t m,
+                                                        double *__restrict__ vout) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < m) vout[e] = vin[at[e]];
+}
+
+// ---------------------------------------------------------------- int scan
+// Exclusive prefix sum of m int32 values in three kernels: per 2048-value
+// block its total, an exclusive scan of the totals in one workgroup, then
+// each block's values from its offset (integers: exact in any order).
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int block_excl_scan(int v, int *s) {
+    const int t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const int u = t >= o ? s[t - o] : 0;
+        __syncthreads();
+        s[t] += u;
+        __syncthreads();
+    }
+    const int incl = s[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_iscan_reduce(const int32_t *__restrict__ in, int64_t m,
+                                                         int32_t *__restrict__ part) {
+    __shared__ int s[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v = 0;
+#pragma unroll
+    for (int a = 0; a < kScanItems; ++a) v += base + a < m ? in[base + a] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_iscan_parts(int32_t *__restrict__ part, int64_t nb) {
+    __shared__ int s[kBlock];
+    const int64_t per = cdiv(nb, kBlock);
+    const int64_t a0 = (int64_t)threadIdx.x * per, a1 = a0 + per < nb ? a0 + per : nb;
+    int v = 0;
+    for (int64_t a = a0; a < a1; ++a) v += part[a];
+    int run = block_excl_scan(v, s);
+    for (int64_t a = a0; a < a1; ++a) {
+        const int c = part[a];
+        part[a] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_iscan_apply(const int32_t *__restrict__ in, int64_t m,
+                                                        const int32_t *__restrict__ part,
+                                                        int32_t *__restrict__ out) {
+    __shared__ int s[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int x[kScanItems], v = 0;
+#pragma unroll
+    for (int a = 0; a < kScanItems; ++a) {
+        x[a] = base + a < m ? in[base + a] : 0;
+        v += x[a];
+    }
+    int run = part[blockIdx.x] + block_excl_scan(v, s);
+#pragma unroll
+    for (int a = 0; a < kScanItems; ++a) {
+        if (base + a < m) out[base + a] = run;
+        run += x[a];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_uflags(const uint64_t *__restrict__ keys, int64_t m,
@@ -346,23 +430,28 @@ hts_status affinities(hts_ctx ctx, hipStream_t st, const void *X, int64_t n, int
     hipLaunchKernelGGL(k_perplexity, dim3(cdiv(n * kWave, kBlock)), dim3(kBlock), 0, st, ld, n, k,
                        std::log(perplexity), pc);
     HTS_HIP(hipGetLastError());
+    // the sort's values are the entries' positions (in the flag buffer, then
+    // the position buffer), free until the flags and their scan are formed
+    uint32_t *at_in = (uint32_t *)flag, *at_out = (uint32_t *)pos;
     hipLaunchKernelGGL(k_coo, dim3(cdiv(nk, kBlock)), dim3(kBlock), 0, st, lj, pc, n, k, kin, vin,
-                       knn_idx);
+                       at_in, knn_idx);
     HTS_HIP(hipGetLastError());
-    unsigned bits = 1;
+    int bits = 1;
     while (bits < 64 && ((uint64_t)1 << bits) < (uint64_t)n * (uint64_t)n) ++bits;
-    size_t tmp_bytes = 0;
-    HTS_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, kin, kout, vin, vout, (size_t)m, 0u, bits, st));
-    HTS_OKR(ensure(ctx->aff[6], tmp_bytes));
-    HTS_HIP(rocprim::radix_sort_pairs(ctx->aff[6].p, tmp_bytes, kin, kout, vin, vout, (size_t)m, 0u,
-                                      bits, st));
+    HTS_OKR(ensure(ctx->aff[6], radix_sort_temp_bytes(m)));
+    HTS_OKR(radix_sort_pairs(st, kin, at_in, kout, at_out, m, bits, ctx->aff[6].p));
+    hipLaunchKernelGGL(k_gather_vals, dim3(cdiv(m, kBlock)), dim3(kBlock), 0, st, at_out, vin, m,
+                       vout);
+    HTS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_uflags, dim3(cdiv(m, kBlock)), dim3(kBlock), 0, st, kout, m, flag);
     HTS_HIP(hipGetLastError());
-    size_t scan_bytes = 0;
-    HTS_HIP(rocprim::exclusive_scan(nullptr, scan_bytes, flag, pos, 0, (size_t)m, rocprim::plus<int32_t>(), st));
-    HTS_OKR(ensure(ctx->aff[7], scan_bytes));
-    HTS_HIP(rocprim::exclusive_scan(ctx->aff[7].p, scan_bytes, flag, pos, 0, (size_t)m,
-                                    rocprim::plus<int32_t>(), st));
+    const int64_t nsb = cdiv(m, kScanTile);
+    HTS_OKR(ensure(ctx->aff[7], (size_t)nsb * 4));
+    int32_t *spart = (int32_t *)ctx->aff[7].p;
+    hipLaunchKernelGGL(k_iscan_reduce, dim3(nsb), dim3(kBlock), 0, st, flag, m, spart);
+    hipLaunchKernelGGL(k_iscan_parts, dim3(1), dim3(kBlock), 0, st, spart, nsb);
+    hipLaunchKernelGGL(k_iscan_apply, dim3(nsb), dim3(kBlock), 0, st, flag, m, spart, pos);
+    HTS_HIP(hipGetLastError());
     int32_t last[2] = {0, 0};
     HTS_HIP(hipMemcpyAsync(&last[0], pos + m - 1, 4, hipMemcpyDeviceToHost, st));
     HTS_HIP(hipMemcpyAsync(&last[1], flag + m - 1, 4, hipMemcpyDeviceToHost, st));
