@@ -373,6 +373,7 @@ def bench_serve(args):
         "one_at_a_time": {k: round(v, 3) for k, v in fifo.items()},
         "speedup_jobs_per_s": round(sb["jobs_per_s"] / fifo["jobs_per_s"], 2),
         "max_active_jobs": srv.max_active, "relayouts": srv.relayouts,
+        "setup_overlapped_s": round(srv.setup_overlap_s, 3),
         "burst_capacity_jobs_per_s": round(cap, 3),
         "roofline": None, "cpu_baseline": None,
     }

@@ -2,10 +2,12 @@
 
 Requests (a data matrix X and an iteration count) arrive over time.  A
 request waits until its device footprint fits the HBM budget next to the
-running jobs, then is admitted: its affinities P are built on the GPU and it
-joins the running job layout (`batch.JobBatch`), where every iteration
-advances all admitted jobs in the same launches, each at its own point of the
-schedule of Sec. 5.  A job leaves the layout after exactly its iteration
+running jobs, then is admitted: its affinities P are built on the GPU by a
+worker thread, on a second stream (default priority) with a context of its
+own (so its workspaces are its own), while the running jobs keep iterating;
+once P is ready the job joins the running job layout (`batch.JobBatch`),
+where every iteration advances all admitted jobs in the same launches, each
+at its own point of the schedule of Sec. 5.  A job leaves the layout after exactly its iteration
 count; its result is copied to the host at that moment.  P, tree and
 positions stay on the device for the job's whole life.
 
@@ -19,6 +21,7 @@ the single-job calls.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import time
 
@@ -91,13 +94,30 @@ class Server:
         self.dev = torch.device("cuda", ctx.device)
         self.max_active = 0
         self.relayouts = 0
+        self.setup_overlap_s = 0.0   # setup time spent while jobs were iterating
 
-    def _admit(self, req: Request) -> dict:
-        X = torch.from_numpy(np.ascontiguousarray(req.X, dtype=np.float32)).to(self.dev)
-        n = X.shape[0]
-        _, rp, col, val = hts.build_affinities(self.ctx, X, self.perplexity, min(self.k, n - 1),
-                                               p_dtype=torch.float32, want_knn=False)
-        job = Job(rp, col, val, _start_embedding(n, req.seed, self.dev), name=str(req.rid))
+    def _prepare(self, req: Request, setup_ctx: hts.Context, stream: torch.cuda.Stream):
+        """Worker thread: P of a request on the setup stream and context; returns
+        the device tensors and an event recorded after them."""
+        with torch.cuda.device(self.dev), torch.cuda.stream(stream):
+            X = torch.from_numpy(np.ascontiguousarray(req.X, dtype=np.float32)).to(self.dev)
+            n = X.shape[0]
+            _, rp, col, val = hts.build_affinities(setup_ctx, X, self.perplexity, min(self.k, n - 1),
+                                                   p_dtype=torch.float32, want_knn=False)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return rp, col, val, ev
+
+    def _join(self, req: Request, prepared) -> dict:
+        """Main thread: the prepared P becomes a job of the layout on the
+        current stream (which waits for the setup stream's work)."""
+        rp, col, val, ev = prepared
+        main = torch.cuda.current_stream(self.dev)
+        main.wait_event(ev)
+        for t in (rp, col, val):
+            t.record_stream(main)   # allocated on the setup stream, used on this one
+        job = Job(rp, col, val, _start_embedding(rp.numel() - 1, req.seed, self.dev),
+                  name=str(req.rid))
         return {"req": req, "job": job, "done": 0, "admitted": None, "state": None}
 
     def _layout(self, active, old: JobBatch | None) -> JobBatch | None:
@@ -114,32 +134,52 @@ class Server:
         return b
 
     def run(self, requests: list[Request]) -> list[Result]:
+        setup_ctx = hts.Context(self.ctx.device)
+        stream = torch.cuda.Stream(self.dev)   # default priority
+        pool = concurrent.futures.ThreadPoolExecutor(max_workers=1)
+        try:
+            return self._run(requests, setup_ctx, stream, pool)
+        finally:
+            pool.shutdown(wait=True)
+            stream.synchronize()
+            setup_ctx.close()
+
+    def _run(self, requests, setup_ctx, stream, pool) -> list[Result]:
         pending = sorted(requests, key=lambda r: r.arrival)
-        waiting, active, results = [], [], []
+        waiting, preparing, active, results = [], [], [], []
         batch = None
         used = 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
-        while pending or waiting or active:
+        while pending or waiting or preparing or active:
             t = now()
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.pop(0))
             changed = False
             # admission in arrival order while the footprint fits (a job
-            # larger than the whole budget runs alone)
+            # larger than the whole budget runs alone): its setup starts on
+            # the worker, its footprint counts from now
             while waiting:
                 fp = footprint_bytes(waiting[0].X.shape[0], self.k, self.max_depth, self.ctx.item_list)
-                if active and used + fp > self.budget:
+                if (active or preparing) and used + fp > self.budget:
                     break
                 req = waiting.pop(0)
-                a = self._admit(req)
+                used += fp
+                preparing.append((req, fp, pool.submit(self._prepare, req, setup_ctx, stream), now()))
+            # jobs whose P is ready join the layout, in admission order
+            while preparing and preparing[0][2].done():
+                req, fp, fut, ts = preparing.pop(0)
+                a = self._join(req, fut.result())
+                if active:
+                    self.setup_overlap_s += now() - ts
                 a["admitted"] = now()
                 a["fp"] = fp
-                used += fp
                 active.append(a)
                 changed = True
             if not active:
-                if pending:
+                if preparing:
+                    concurrent.futures.wait([preparing[0][2]], timeout=0.01)
+                elif pending:
                     time.sleep(max(0.0, min(pending[0].arrival - now(), 0.01)))
                 continue
             if changed:
@@ -150,19 +190,22 @@ class Server:
                 for a in active:
                     a["state"] = None
                 self.max_active = max(self.max_active, len(active))
-            # iterate until the next job completes or a new request arrives
+            # iterate until the next job completes, a new request arrives or
+            # a setup finishes
             left = min(a["req"].iters - a["done"] for a in active)
             steps = 0
             while steps < left:
                 batch.iterate()
                 steps += 1
-                if pending and pending[0].arrival <= now() and steps % 8 == 0:
+                if steps % 8 == 0 and ((pending and pending[0].arrival <= now()) or
+                                       (preparing and preparing[0][2].done())):
                     break
             for a in active:
                 a["done"] += steps
             finished = [i for i, a in enumerate(active) if a["done"] >= a["req"].iters]
             if finished:
-                torch.cuda.synchronize()
+                # this stream only: a setup running beside it is not waited for
+                torch.cuda.current_stream(self.dev).synchronize()
                 tf = now()
                 keep = []
                 for i, a in enumerate(active):
