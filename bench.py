@@ -161,21 +161,24 @@ def cpu_baseline(snaps, rp, col, val, theta, gpu_grads, hsne_lambda=None, bh_row
         if gpu_grads is not None:
             rec["gpu_fp32_vs_oracle_rel_l2"] = rel_l2(gpu_grads[k], g)
             rec["gpu_fp32_vs_oracle_rel_row"] = rel_row(gpu_grads[k], g)
-        # one thread: tree + sampled traversals scaled to n + step
+        # one thread: tree + sampled traversals scaled to n + step (the
+        # oracle samples rows of the hyperbolic gradient only, so for h-SNE
+        # there is no one-thread figure)
         oracle.set_threads(1)
-        rows = synth.subsample(n, bh_rows, seed=300 + k)
-        t0 = time.perf_counter()
-        tree1 = oracle.Tree(Y)
-        t_tree = time.perf_counter() - t0
-        t0 = time.perf_counter()
+        tree1 = None
         if hsne_lambda is None:
+            rows = synth.subsample(n, bh_rows, seed=300 + k)
+            t0 = time.perf_counter()
+            tree1 = oracle.Tree(Y)
+            t_tree = time.perf_counter() - t0
+            t0 = time.perf_counter()
             oracle.gradient_bh_rows(Y, rp, col, val, tree1, theta, rows, z, ex)
-        t_rows = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.step(Y, U, G, g, n / 12000.0, mu)
-        t_step = time.perf_counter() - t0
-        t_one.append(t_tree + t_rows * n / rows.size + t_step)
-        rec["one_thread_s_est"] = round(t_one[-1], 3)
+            t_rows = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.step(Y, U, G, g, n / 12000.0, mu)
+            t_step = time.perf_counter() - t0
+            t_one.append(t_tree + t_rows * n / rows.size + t_step)
+            rec["one_thread_s_est"] = round(t_one[-1], 3)
         # exact gradient rows, one thread and all cores
         for nt, m, acc in ((1, exact_rows[0], t_ex1), (threads, exact_rows[1], t_exa)):
             oracle.set_threads(nt)
@@ -190,15 +193,15 @@ def cpu_baseline(snaps, rp, col, val, theta, gpu_grads, hsne_lambda=None, bh_row
     out.update({
         "value": nsnap / sum(t_all), "unit": "iters/s", "cores": threads, "kind": "oracle",
         "cpu_model": cpu_model(),
-        "one_thread_iters_per_s": nsnap / sum(t_one),
+        "one_thread_iters_per_s": nsnap / sum(t_one) if t_one else None,
         "exact_s_per_iter_one_thread": sum(t_ex1) / nsnap,
         "exact_s_per_iter_all_cores": sum(t_exa) / nsnap,
         "sample": "FP64 oracle on the GPU windows' snapshot embeddings (iterations %s of the "
                   "schedule, FP32 bytes promoted) and the GPU-built P (nnz=%d): one whole "
                   "iteration per snapshot on %d threads (insertion tree + %s at theta=%.1f + "
-                  "step; the value); one thread: tree + step + %d sampled query traversals "
-                  "scaled to N; exact gradient from %d / %d sampled rows (1 thread / %d) scaled "
-                  "to N" % (",".join(str(s[0]) for s in snaps), int(rp[-1]), threads,
+                  "step; the value); one thread (hyperbolic iteration only): tree + step + %d "
+                  "sampled query traversals scaled to N; exact hyperbolic gradient from %d / %d "
+                  "sampled rows (1 thread / %d) scaled to N" % (",".join(str(s[0]) for s in snaps), int(rp[-1]), threads,
                             "Barnes-Hut gradient" if hsne_lambda is None else
                             "h-SNE Barnes-Hut gradient", theta, bh_rows, exact_rows[0],
                             exact_rows[1], threads),
