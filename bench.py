@@ -237,7 +237,7 @@ def bench_jobs(args):
     import numpy as np
     import torch
     from paper_2401_13708_amd import hts
-    from paper_2401_13708_amd.batch import JobBatch, autotune_item_points
+    from paper_2401_13708_amd.batch import JobBatch, autotune_traversal
     from paper_2401_13708_amd.embed import Embedding
     dev = torch.device("cuda", 0)
     ctx = hts.Context(0)
@@ -249,7 +249,7 @@ def bench_jobs(args):
     print("bench: %d jobs, %d points in all, set up in %.1fs" % (len(jobs), total_n, setup_s),
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    best, table = autotune_item_points(ctx, jobs, theta=args.theta)
+    (best, best_launch), table = autotune_traversal(ctx, jobs, theta=args.theta)
     tune_s = time.perf_counter() - t0
     print("bench: work-item size %d (ms/iteration %s)" % (best, {k: round(v, 3) for k, v in table.items()}),
           file=sys.stderr, flush=True)
@@ -306,7 +306,8 @@ def bench_jobs(args):
         "batched_eager_jobs_per_s": round(len(jobs) / t_batch, 3),
         "speedup_vs_sequential": round(t_seq / t_graph, 2),
         "max_abs_diff_vs_sequential": max(diff, diff_g),
-        "autotune": {"item_points": best, "ms_per_iteration": {str(k): round(v, 4) for k, v in table.items()},
+        "autotune": {"item_points": best, "traversal_launch": list(best_launch),
+                     "ms_per_iteration": {str(k): round(v, 4) for k, v in table.items()},
                      "tune_s": round(tune_s, 2)},
         "setup_s": round(setup_s, 2),
         "roofline": None, "cpu_baseline": None,
@@ -426,6 +427,9 @@ def bench_single(args):
         ctx.set_item_list(args.item_list)
     if args.item_points is not None:
         ctx.set_item_points(args.item_points)
+    if args.items_grid is not None or args.items_waves is not None:
+        ctx.set_traversal_launch(args.items_grid or hts.DEFAULT_ITEMS_GRID,
+                                 args.items_waves or hts.DEFAULT_ITEMS_WAVES)
     Xd = torch.from_numpy(X).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -731,7 +735,8 @@ def bench_single(args):
                    "n": n, "d": d, "theta": args.theta, "perplexity": 30, "k": 90, "nnz": nnz,
                    "split_rule": "equal lengths, eq. (10)" if args.split_rule == 0
                    else "equal areas, eq. (9)", "hsne_lambda": hs, "item_list": ctx.item_list,
-                   "item_points": ctx.item_points, "windows": windows},
+                   "item_points": ctx.item_points, "traversal_launch": list(ctx.traversal_launch),
+                   "windows": windows},
         "windows": win_out,
         "exact_iters_per_s": round(exact_ips, 3) if exact_ips else None,
         "speedup_vs_exact": round(value / exact_ips, 1) if exact_ips else None,
@@ -898,6 +903,10 @@ def main():
                          "write the embedding reached (the native run continues the schedule there)")
     ap.add_argument("--item-points", type=int, default=None,
                     help="Barnes-Hut work-item size S (library default 256)")
+    ap.add_argument("--items-grid", type=int, default=None,
+                    help="workgroups of the traversal's second kernel (library default 16384)")
+    ap.add_argument("--items-waves", type=int, default=None,
+                    help="waves per workgroup of that kernel: 1, 2 or 4 (library default 4)")
     ap.add_argument("--item-list", type=int, default=None,
                     help="item-list entries per phase-A wave (library default 256)")
     ap.add_argument("--hsne-lambda", type=float, default=None,

@@ -309,6 +309,16 @@ hts_status hts_set_item_points(hts_ctx ctx, int32_t item_points);
  * wave records; larger values act as 256); applies to later calls on ctx. */
 hts_status hts_set_item_list(hts_ctx ctx, int32_t items_per_wave);
 
+/* Launch shape of the traversal's second kernel (the short walks of the item
+ * list): at most `workgroups` workgroups of `waves_per_workgroup` 64-lane
+ * waves (1, 2 or 4), striding over the list.  workgroups = 0 (the default)
+ * sizes the grid to 32 waves per wave of the first kernel, about one wave per
+ * walk, so that each freed wave slot takes the next walk; with the default of
+ * one wave per workgroup no slot waits for a workgroup's other waves.  Every
+ * walk writes its own partials, so the result does not depend on the shape at
+ * all (bit for bit).  Applies to later calls on ctx. */
+hts_status hts_set_traversal_launch(hts_ctx ctx, int32_t workgroups, int32_t waves_per_workgroup);
+
 /* Workspace generation of ctx (host, *gen_out).  The context keeps device
  * workspaces that grow on demand, and a job layout (hts_tree_set_jobs)
  * replaces its tree's tables; either reallocation changes this counter.

@@ -160,22 +160,32 @@ class JobBatch:
             self.tree = None
 
 
-def autotune_item_points(ctx: hts.Context, jobs: list[Job], candidates=(128, 256, 512, 1024, 2048),
-                         warm: int = 100, reps: int = 8, theta: float = 0.5) -> tuple[int, dict]:
-    """Picks the Barnes-Hut work-item size for a batch of jobs by timing.
+# launch shapes of the traversal's second kernel: (workgroups, waves per workgroup)
+TRAVERSAL_LAUNCHES = ((0, 1), (16384, 4), (65536, 2), (32768, 1), (65536, 1), (131072, 1),
+                      (262144, 1))
+
+
+def autotune_traversal(ctx: hts.Context, jobs: list[Job], candidates=(128, 256, 512, 1024, 2048),
+                       launches=TRAVERSAL_LAUNCHES, warm: int = 100, reps: int = 8,
+                       theta: float = 0.5) -> tuple[tuple[int, tuple[int, int]], dict]:
+    """Picks the Barnes-Hut traversal's tile and launch shapes for a batch of
+    jobs by timing: the work-item size S (the walks handed to the second
+    kernel hold at most S points), then, at the best S, the second kernel's
+    workgroup count (0: the library's automatic count) and waves per workgroup.
 
     A scratch copy of the batch is advanced `warm` iterations (the embedding
     spreads out, which changes the traversal), then every candidate times
-    `reps` iterations from that same state.  The fastest is set on ctx and
-    returned with the per-candidate milliseconds per iteration."""
+    `reps` iterations from that same state.  The fastest setting is left on
+    ctx and returned with the milliseconds per iteration of every candidate
+    ({"S=..": ms, "grid=..x..": ms}).  S changes only the order of
+    floating-point sums; the launch shape changes nothing in the result."""
     b = JobBatch(ctx, jobs, theta=theta)
-    prev = getattr(ctx, "item_points", hts.DEFAULT_ITEM_POINTS)
     ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
+    ctx.set_traversal_launch(hts.DEFAULT_ITEMS_GRID, hts.DEFAULT_ITEMS_WAVES)
     b.run(warm)
     saved = [t.clone() for t in (b.Y, b.update, b.gains, b.it)]
-    times = {}
-    for S in candidates:
-        ctx.set_item_points(S)
+
+    def timed():
         for t, v in zip((b.Y, b.update, b.gains, b.it), saved):
             t.copy_(v)
         b.iterate()
@@ -185,8 +195,20 @@ def autotune_item_points(ctx: hts.Context, jobs: list[Job], candidates=(128, 256
             b.iterate()
         e1.record()
         torch.cuda.synchronize()
-        times[S] = e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / reps
+
+    times = {}
+    by_s = {}
+    for S in candidates:
+        ctx.set_item_points(S)
+        by_s[S] = times["S=%d" % S] = timed()
+    best_s = min(by_s, key=by_s.get) if by_s else hts.DEFAULT_ITEM_POINTS
+    ctx.set_item_points(best_s)
+    by_l = {}
+    for g, w in launches:
+        ctx.set_traversal_launch(g, w)
+        by_l[(g, w)] = times["grid=%dx%d" % (g, w)] = timed()
+    best_l = min(by_l, key=by_l.get) if by_l else (hts.DEFAULT_ITEMS_GRID, hts.DEFAULT_ITEMS_WAVES)
+    ctx.set_traversal_launch(*best_l)
     b.close()
-    best = min(times, key=times.get) if times else prev
-    ctx.set_item_points(best)
-    return best, times
+    return (best_s, best_l), times

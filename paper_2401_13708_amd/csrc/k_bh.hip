@@ -390,7 +390,8 @@ __device__ __forceinline__ ItemRec load_item(const ItemRec *__restrict__ dense, 
     return u;
 }
 
-// Phase B: wave w walks items w, w + G, ... of the item list.
+// Phase B: wave w walks items w, w + G, ... of the item list (G waves in the
+// grid; a workgroup holds 1, 2 or 4 waves).
 template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_items(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
@@ -401,9 +402,10 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
     const int M = uniform(*d_m);
     const int64_t reserved = (int64_t)(uint32_t)uniform((int)*dense_count);
     const int64_t total = reserved < cap ? reserved : cap;  // never more, by the shares
-    const int64_t G = (int64_t)gridDim.x * (kBlock / kWave);
+    const int wpb = (int)(blockDim.x / kWave);
+    const int64_t G = (int64_t)gridDim.x * wpb;
     int dummy = 0;
-    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < total; i += G) {
+    for (int64_t i = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; i < total; i += G) {
         const ItemRec rec = load_item(dense, i);
         const PointRec<T> me = spts[lane < rec.cnt ? rec.q0 + lane : rec.q0];
         const int64_t q = (int64_t)rec.q0 + lane;
@@ -634,8 +636,12 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const NodeRec<T> *nodes = (const NodeRec<T> *)(MET == 0 ? t->nodes : t->enodes);
     const PointRec<T> *spts = (const PointRec<T> *)t->spts;
     const dim3 gq(nqb);  // the combine: one workgroup per query block
-    int64_t gi = cdiv(slots, kBlock / kWave);
-    if (gi > 16384) gi = 16384;  // several waves per SIMD slot: the hardware balances the load
+    // phase B: items_grid workgroups of items_waves waves, by default 32
+    // waves per phase-A wave (about one per item: the hardware hands each
+    // freed wave slot the next item), never more than the list holds
+    const int wpb = ctx->items_waves;
+    int64_t gi = ctx->items_grid > 0 ? (int64_t)ctx->items_grid : cdiv(32 * nw, wpb);
+    if (gi > cdiv(slots, wpb)) gi = cdiv(slots, wpb);
     if (gi < 1) gi = 1;          // an empty list (no items can be handed over)
     // one thread per point, and the node thresholds strided over the same grid
     const int64_t gp = cdiv(n, kBlock) > 64 ? cdiv(n, kBlock) : 64;
@@ -660,10 +666,10 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     {
         TimedScope ts(ctx, st, HTS_K_ITEMS);
         if (stats)
-            hipLaunchKernelGGL((k_bh_items<T, MET, true>), dim3(gi), dim3(kBlock), 0, st, nodes, t->d_m,
+            hipLaunchKernelGGL((k_bh_items<T, MET, true>), dim3(gi), dim3(wpb * kWave), 0, st, nodes, t->d_m,
                                spts, dense_count, dense, slots, part, zitem, st_items);
         else
-            hipLaunchKernelGGL((k_bh_items<T, MET, false>), dim3(gi), dim3(kBlock), 0, st, nodes,
+            hipLaunchKernelGGL((k_bh_items<T, MET, false>), dim3(gi), dim3(wpb * kWave), 0, st, nodes,
                                t->d_m, spts, dense_count, dense, slots, part, zitem, nullptr);
     }
     HTS_HIP(hipGetLastError());

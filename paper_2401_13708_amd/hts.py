@@ -58,6 +58,7 @@ _SIGS = {
     "hts_jobs_schedule": (C.c_int, [_P, _P, _I32, _P, _I32, _D, _D, _D, _P, _P]),
     "hts_set_item_points": (C.c_int, [_P, _I32]),
     "hts_set_item_list": (C.c_int, [_P, _I32]),
+    "hts_set_traversal_launch": (C.c_int, [_P, _I32, _I32]),
     "hts_cosne_terms": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _D, _D, _P]),
     "hts_tree_set_split": (C.c_int, [_P, _I32]),
     "hts_workspace_generation": (C.c_int, [_P, C.POINTER(C.c_uint64)]),
@@ -131,6 +132,8 @@ STATS_BLOCK = 6
 STATS_PER_CALL = 2 * STATS_BLOCK
 DEFAULT_ITEM_POINTS = 256  # the library's default work-item size
 DEFAULT_ITEM_LIST = 256    # the library's default item-list entries per phase-A wave
+DEFAULT_ITEMS_GRID = 0     # the library's default phase-B workgroups (0: automatic) ...
+DEFAULT_ITEMS_WAVES = 1    # ... of this many waves
 
 
 class Context:
@@ -143,6 +146,7 @@ class Context:
         self.device = device
         self.item_points = DEFAULT_ITEM_POINTS
         self.item_list = DEFAULT_ITEM_LIST
+        self.traversal_launch = (DEFAULT_ITEMS_GRID, DEFAULT_ITEMS_WAVES)
 
     def close(self):
         if getattr(self, "h", None):
@@ -166,6 +170,13 @@ class Context:
         """Item-list entries per phase-A wave (device memory of the traversal)."""
         _ck(lib().hts_set_item_list(self.h, int(items_per_wave)))
         self.item_list = int(items_per_wave)
+
+    def set_traversal_launch(self, workgroups: int = DEFAULT_ITEMS_GRID,
+                             waves_per_workgroup: int = DEFAULT_ITEMS_WAVES):
+        """Launch shape of the traversal's second kernel (a tuning parameter;
+        the result does not depend on it)."""
+        _ck(lib().hts_set_traversal_launch(self.h, int(workgroups), int(waves_per_workgroup)))
+        self.traversal_launch = (int(workgroups), int(waves_per_workgroup))
 
     def set_item_points(self, s: int):
         """Barnes-Hut work-item size (a tuning parameter)."""

@@ -301,6 +301,32 @@ def test_bh_item_list_sizes(ctx, item_list, item_points):
     assert np.array_equal(g, g2) and z == z2
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_bh_traversal_launch_shapes_give_the_same_result(ctx, dtype):
+    # the second kernel's workgroup count and waves per workgroup only decide
+    # which wave walks which item: the gradient, Z and the counters are the
+    # same bit for bit (down to a single one-wave workgroup walking the whole
+    # list)
+    X, _, rp, col, val = affinities(3000)
+    Y = embedding(3000, "late", dtype)
+    val = val.astype(dtype)
+    try:
+        ref = _run_bh(ctx, Y, rp, col, val, 12.0, 0.5, stats=True)
+        for g_, w_ in [(1, 1), (3, 2), (7, 4), (65536, 1), (16384, 4), (0, 2)]:
+            ctx.set_traversal_launch(g_, w_)
+            got = _run_bh(ctx, Y, rp, col, val, 12.0, 0.5, stats=True)
+            assert np.array_equal(got[0], ref[0]) and got[1] == ref[1] and got[2] == ref[2], (g_, w_)
+    finally:
+        ctx.set_traversal_launch()
+
+
+def test_traversal_launch_rejects_bad_shapes(ctx):
+    for g_, w_ in [(-1, 4), (16, 3), (16, 8), (0, 0)]:
+        with pytest.raises(RuntimeError):
+            ctx.set_traversal_launch(g_, w_)
+    assert ctx.traversal_launch == (hts.DEFAULT_ITEMS_GRID, hts.DEFAULT_ITEMS_WAVES)
+
+
 def test_item_list_rejects_negative(ctx):
     with pytest.raises(RuntimeError):
         ctx.set_item_list(-1)
