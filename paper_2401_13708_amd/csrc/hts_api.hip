@@ -205,7 +205,6 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
         {(void **)&t->r_cell, (size_t)cap * 8},
         {(void **)&t->node_first, (size_t)cap * 4},
         {(void **)&t->sinhalf, 32 * 8},
-        {(void **)&t->rays, (size_t)ray_entries(kRayLevels) * sizeof(double2)},
     };
     hts_status s = HTS_OK;
     for (auto &a : allocs) {
@@ -233,10 +232,7 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) s = hip_fail(e, "tree init");
     }
-    if (s == HTS_OK) {
-        t->ray_levels = max_depth - 1 < kRayLevels ? max_depth - 1 : kRayLevels;
-        s = tree_rays(t->rays, t->ray_levels);
-    }
+
     if (s != HTS_OK) {
         hts_tree_destroy(t);
         return s;
@@ -252,7 +248,7 @@ hts_status hts_tree_destroy(hts_tree t) {
     void *ptrs[] = {t->job_off, t->job_qb, t->qb_job, t->pjob, t->root, t->r, t->mm,
                     t->keys_in, t->keys, t->idx_in, t->perm, t->sort_tmp, t->ncnt_part,
                     t->q_part, t->node_start, t->psum, t->d_m, t->spts, t->nodes, t->r_cell,
-                    t->node_first, t->sinhalf, t->rays, t->enodes, t->epsum, t->epart};
+                    t->node_first, t->sinhalf, t->enodes, t->epsum, t->epart};
     for (void *p : ptrs)
         if (p) hipFree(p);
     delete t;

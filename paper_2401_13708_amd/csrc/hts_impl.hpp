@@ -144,8 +144,6 @@ struct hts_tree_s {
     double *r_cell = nullptr;      // [cap_nodes]
     int32_t *node_first = nullptr; // [cap_nodes]
     double *sinhalf = nullptr;     // [32] sin(pi / 2^l), 1 for l <= 1
-    double2 *rays = nullptr;       // split rays of the angular levels 1..ray_levels (k_tree.hip)
-    int32_t ray_levels = 0;
     int32_t job_bits = 0;          // key bits above the 2 max_depth cell bits
     int32_t split_rule = 0;        // 0: equal radial lengths (eq. (10)); 1: equal areas (eq. (9))
     // Euclidean summaries for the h-SNE term, allocated on first use
@@ -204,10 +202,6 @@ inline Jobs jobs_of(hts_tree t) {
 // build, for the h-SNE term
 template <typename T>
 hts_status tree_euclid(hts_ctx ctx, hipStream_t st, hts_tree t, double theta);
-// the split rays of the angular levels 1..levels (the same for every tree)
-constexpr int kRayLevels = 15;
-__host__ __device__ inline int64_t ray_entries(int levels) { return ((int64_t)2 << levels) - 2; }
-hts_status tree_rays(double2 *rays, int levels);
 
 // stable LSD radix sort of (key, value) pairs by the low `bits` key bits
 size_t radix_sort_temp_bytes(int64_t n);

@@ -164,39 +164,6 @@ __device__ __forceinline__ int ang_bit(int depth, const double *mid, double xs, 
     return __dsub_rn(__dmul_rn(c, ys), __dmul_rn(s, xs)) >= 0.0;
 }
 
-// The root's angular range is always the whole circle, so the split ray of a
-// cell depends only on its level and on the angular bits above it: the rays
-// of levels 1..levels are tabulated once per tree, entry 2^l - 2 + prefix for
-// the cell of level l whose angular bits from the root are `prefix` (the
-// first bit highest).  Each entry walks its cell's path from the root with
-// ang_mid, the operations of the recursion itself, so the table holds the
-// recursion's values bit for bit.
-__global__ __launch_bounds__(kBlock) void k_rays(double2 *__restrict__ rays, int levels) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= ray_entries(levels)) return;
-    int l = 1;
-    while (ray_entries(l) <= e) ++l;
-    const int64_t prefix = e - (((int64_t)1 << l) - 2);
-    double lo[2] = {1.0, 0.0}, hi[2] = {1.0, 0.0}, am[2];
-    for (int d = 0; d < l; ++d) {
-        ang_mid(d, lo, hi, am);
-        double *bound = ((prefix >> (l - 1 - d)) & 1) ? lo : hi;
-        bound[0] = am[0];
-        bound[1] = am[1];
-    }
-    ang_mid(l, lo, hi, am);
-    rays[e] = make_double2(am[0], am[1]);
-}
-
-hts_status tree_rays(double2 *rays, int levels) {
-    if (levels < 1) return HTS_OK;
-    hipLaunchKernelGGL(k_rays, dim3(cdiv(ray_entries(levels), kBlock)), dim3(kBlock), 0, 0, rays,
-                       levels);
-    HTS_HIP(hipGetLastError());
-    HTS_HIP(hipDeviceSynchronize());
-    return HTS_OK;
-}
-
 // ---------------------------------------------------------------- 2. keys
 // job index above max_depth levels of the split rule, two bits per level
 // (radial bit: r at or above the radial split; angular bit: the upper half
@@ -212,8 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
                                                  const double *__restrict__ mm,
                                                  double *__restrict__ root, int L, int split,
                                                  uint64_t *__restrict__ keys,
-                                                 uint32_t *__restrict__ idx,
-                                                 const double2 *__restrict__ rays, int ray_levels) {
+                                                 uint32_t *__restrict__ idx) {
     __shared__ double s_range[2][2];
     const int64_t b0 = (int64_t)blockIdx.x * kBlock;
     const int64_t bl = (b0 + kBlock < n ? b0 + kBlock : n) - 1;
@@ -252,19 +218,11 @@ __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ r,
     const double xs = (double)(float)Y[2 * i], ys = (double)(float)Y[2 * i + 1];
     double alo[2] = {1.0, 0.0}, ahi[2] = {1.0, 0.0};  // the root's bounds: angle 0 = 2 pi
     uint64_t key = (uint64_t)job;
-    int64_t apre = 0;  // the angular bits so far
     for (int l = 0; l < L; ++l) {
         const double mr = radial_mid(lo, hi, split);
         double am[2];
-        if (l >= 1 && l <= ray_levels) {
-            const double2 m = rays[(((int64_t)1 << l) - 2) + apre];
-            am[0] = m.x;
-            am[1] = m.y;
-        } else {
-            ang_mid(l, alo, ahi, am);
-        }
+        ang_mid(l, alo, ahi, am);
         const int rb = rv >= mr, pb = ang_bit(l, am, xs, ys);
-        apre = (apre << 1) | pb;
         key = (key << 2) | (uint64_t)(2 * rb + pb);
         if (rb) lo = mr; else hi = mr;
         double *bound = pb ? alo : ahi;
@@ -603,8 +561,7 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
                        t->mm, t->root);
     HTS_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_keys<T>, dim3(nb), dim3(kBlock), 0, st, t->r, Y, n, t->pjob, t->job_off,
-                       t->mm, t->root, L, t->split_rule, t->keys_in, t->idx_in, t->rays,
-                       t->ray_levels);
+                       t->mm, t->root, L, t->split_rule, t->keys_in, t->idx_in);
     HTS_HIP(hipGetLastError());
     HTS_OKR(radix_sort_pairs(st, t->keys_in, t->idx_in, t->keys, t->perm, n, 2 * L + t->job_bits,
                              t->sort_tmp));
