@@ -453,7 +453,7 @@ def bench_single(args):
 
     Y0d = torch.from_numpy(Y0).to(dev)
     emb = Embedding(ctx, rp, col, val, Y0d, theta=args.theta, split_rule=args.split_rule,
-                    hsne_lambda=hs)
+                    hsne_lambda=hs, fused=not args.separate_calls)
     ee = emb.sched.ee_iters
 
     # the schedule up to the last snapshot with the counting kernels (same
@@ -903,10 +903,13 @@ def main():
                          "write the embedding reached (the native run continues the schedule there)")
     ap.add_argument("--item-points", type=int, default=None,
                     help="Barnes-Hut work-item size S (library default 256)")
+    ap.add_argument("--separate-calls", action="store_true",
+                    help="iterate with the three separate calls instead of hts_iteration_bh")
     ap.add_argument("--items-grid", type=int, default=None,
-                    help="workgroups of the traversal's second kernel (library default 16384)")
+                    help="workgroups of the traversal's second kernel (library default 0: 32 one-wave "
+                         "workgroups per first-kernel wave)")
     ap.add_argument("--items-waves", type=int, default=None,
-                    help="waves per workgroup of that kernel: 1, 2 or 4 (library default 4)")
+                    help="waves per workgroup of that kernel: 1, 2 or 4 (library default 1)")
     ap.add_argument("--item-list", type=int, default=None,
                     help="item-list entries per phase-A wave (library default 256)")
     ap.add_argument("--hsne-lambda", type=float, default=None,

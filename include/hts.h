@@ -274,6 +274,19 @@ hts_status hts_step(hts_ctx ctx, hts_stream stream, void *Y, void *update,
                     double eta, double momentum, double min_gain,
                     double boundary_eps, int32_t metric_power);
 
+/* One whole iteration of the Barnes-Hut path -- Sec. 4-B and Sec. 5: the
+ * polar tree of Y (as hts_build_polar_tree), the gradient (as
+ * hts_gradient_bh, into grad and z_dev[0]) and the step (as hts_step), in one
+ * asynchronous call on the stream, with results bit for bit those of the
+ * three calls.  One job only; tree as for hts_build_polar_tree
+ * (n <= n_max); the other arguments as for the three calls. */
+hts_status hts_iteration_bh(hts_ctx ctx, hts_stream stream, void *Y, void *update, void *gains,
+                            int64_t n, int32_t dtype, const int64_t *row_ptr,
+                            const int32_t *col_idx, const void *p_val, double exaggeration,
+                            hts_tree tree, double theta, void *grad, double *z_dev, double eta,
+                            double momentum, double min_gain, double boundary_eps,
+                            int32_t metric_power);
+
 /* The step for every job of a tree's layout: n must be the layout's total;
  * eta_dev and momentum_dev are device double[n_jobs] (each job's learning
  * rate and momentum). */

@@ -594,6 +594,62 @@ hts_status hts_cosne_terms(hts_ctx c, hts_stream stream, const void *Y, int64_t 
     return launch_cosne<float>(c, st, (const float *)Y, n, xnorm2, lambda1, lambda2, (float *)grad);
 }
 
+// ---------------------------------------------------------------- iteration
+}  // extern "C"
+
+// One iteration: tree, gradient and step, as the three calls make them.
+template <typename T>
+static hts_status iteration_impl(hts_ctx c, hipStream_t st, T *Y, T *U, T *G, int64_t n,
+                                 const int64_t *rp, const int32_t *col, const T *val, double ex,
+                                 hts_tree t, double theta, T *grad, double *z_dev, double eta,
+                                 double momentum, double min_gain, double boundary_eps,
+                                 int32_t metric_power) {
+    HTS_OKR(tree_build<T>(c, st, Y, n, t));
+    HTS_OKR(bh_impl<T>(c, st, Y, n, rp, col, val, ex, nullptr, t, theta, grad, z_dev, nullptr));
+    return launch_step<T>(c, st, Y, U, G, grad, n, eta, momentum, nullptr, nullptr, nullptr,
+                          min_gain, boundary_eps, metric_power);
+}
+
+extern "C" {
+hts_status hts_iteration_bh(hts_ctx c, hts_stream stream, void *Y, void *update, void *gains,
+                            int64_t n, int32_t dtype, const int64_t *row_ptr,
+                            const int32_t *col_idx, const void *p_val, double exaggeration,
+                            hts_tree t, double theta, void *grad, double *z_dev, double eta,
+                            double momentum, double min_gain, double boundary_eps,
+                            int32_t metric_power) {
+    HTS_OKR(grad_args("hts_iteration_bh", c, Y, n, dtype, row_ptr, col_idx, p_val, exaggeration,
+                      grad, z_dev));
+    if (!(theta >= 0.0) || !std::isfinite(theta))
+        return fail(HTS_EINVAL, "hts_iteration_bh: theta %g must be finite and >= 0", theta);
+    if (!t) return fail(HTS_EINVAL, "hts_iteration_bh: tree is NULL");
+    if (t->ctx != c) return fail(HTS_EINVAL, "hts_iteration_bh: tree belongs to another context");
+    if (t->jobs_set && t->J != 1)
+        return fail(HTS_EINVAL, "hts_iteration_bh: the tree holds a layout of %d jobs", t->J);
+    if (n < 2 || n > t->n_max)
+        return fail(HTS_EINVAL, "hts_iteration_bh: n = %lld not in [2, n_max = %lld]", (long long)n,
+                    (long long)t->n_max);
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(HTS_EINVAL, "hts_iteration_bh: eta must be > 0");
+    if (!(momentum >= 0.0) || !(momentum < 1.0))
+        return fail(HTS_EINVAL, "hts_iteration_bh: momentum not in [0, 1)");
+    if (!(min_gain >= 0.0)) return fail(HTS_EINVAL, "hts_iteration_bh: min_gain < 0");
+    if (!(boundary_eps > 0.0) || !(boundary_eps < 1.0))
+        return fail(HTS_EINVAL, "hts_iteration_bh: boundary_eps not in (0, 1)");
+    if (metric_power != 1 && metric_power != 2)
+        return fail(HTS_EINVAL, "hts_iteration_bh: metric_power must be 1 or 2");
+    if (!update || !gains) return fail(HTS_EINVAL, "hts_iteration_bh: NULL pointer argument");
+    HTS_HIP(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == HTS_F64)
+        return iteration_impl<double>(c, st, (double *)Y, (double *)update, (double *)gains, n,
+                                      row_ptr, col_idx, (const double *)p_val, exaggeration, t,
+                                      theta, (double *)grad, z_dev, eta, momentum, min_gain,
+                                      boundary_eps, metric_power);
+    return iteration_impl<float>(c, st, (float *)Y, (float *)update, (float *)gains, n, row_ptr,
+                                 col_idx, (const float *)p_val, exaggeration, t, theta,
+                                 (float *)grad, z_dev, eta, momentum, min_gain, boundary_eps,
+                                 metric_power);
+}
+
 // ---------------------------------------------------------------- step
 hts_status hts_step(hts_ctx c, hts_stream stream, void *Y, void *update, void *gains,
                     const void *grad, int64_t n, int32_t dtype, double eta, double momentum,

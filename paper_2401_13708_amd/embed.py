@@ -42,8 +42,11 @@ class Embedding:
 
     def __init__(self, ctx: hts.Context, row_ptr, col_idx, p_val, Y0, theta: float = 0.5,
                  exact: bool = False, max_depth: int = 20, schedule: Schedule | None = None,
-                 split_rule: int = 0, hsne_lambda: float | None = None):
+                 split_rule: int = 0, hsne_lambda: float | None = None, fused: bool = True):
         self.ctx = ctx
+        # the Barnes-Hut iteration through hts_iteration_bh (False: the three
+        # separate calls; the same results bit for bit)
+        self.fused = fused
         self.rp, self.col, self.val = row_ptr, col_idx, p_val
         self.Y = Y0.clone()
         self.update = torch.zeros_like(self.Y)
@@ -67,6 +70,15 @@ class Embedding:
 
     def iterate(self, stats=None):
         ex, mu, eta = self.sched.at(self.it, self.n)
+        s = self.sched
+        if self.fused and not self.exact and self.hsne_lambda is None and stats is None:
+            # tree, gradient and step in one call; bit for bit the three
+            # calls below
+            hts.iteration_bh(self.ctx, self.Y, self.update, self.gains, self.rp, self.col, self.val,
+                             self.tree, self.theta, ex, eta, mu, self.grad, self.z, s.min_gain,
+                             s.boundary_eps, s.metric_power)
+            self.it += 1
+            return
         if self.exact:
             hts.gradient_exact(self.ctx, self.Y, self.rp, self.col, self.val, ex, self.grad, self.z)
         else:

@@ -51,6 +51,8 @@ _SIGS = {
     "hts_gradient_hsne": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _D, _D, _P, _D, _P, _P,
                                     _P]),
     "hts_step": (C.c_int, [_P, _P, _P, _P, _P, _P, _I64, _I32, _D, _D, _D, _D, _I32]),
+    "hts_iteration_bh": (C.c_int, [_P, _P, _P, _P, _P, _I64, _I32, _P, _P, _P, _D, _P, _D, _P, _P,
+                                   _D, _D, _D, _D, _I32]),
     "hts_tree_set_jobs": (C.c_int, [_P, _I32, C.POINTER(_I64)]),
     "hts_gradient_bh_jobs": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P, _D, _P, _P,
                                        _P]),
@@ -368,6 +370,25 @@ def step(ctx: Context, Y, update, gains, grad, eta: float, momentum: float,
     _ck(lib().hts_step(ctx.h, _stream(stream), _ptr(Y), _ptr(update), _ptr(gains), _ptr(grad),
                        Y.shape[0], _dtype(Y), float(eta), float(momentum), float(min_gain),
                        float(boundary_eps), int(metric_power)))
+
+
+def iteration_bh(ctx: Context, Y, update, gains, row_ptr, col_idx, p_val, tree: Tree,
+                 theta: float, exaggeration: float, eta: float, momentum: float, grad=None, z=None,
+                 min_gain: float = 0.01, boundary_eps: float = 1e-5, metric_power: int = 2,
+                 stream=None):
+    """Tree, Barnes-Hut gradient and step in one call (the attractive term
+    overlaps the tree build on a second stream); returns grad, z."""
+    for t, nm in ((Y, "Y"), (update, "update"), (gains, "gains")):
+        _dev(t, nm, Y.dtype)
+    _csr_args(Y, row_ptr, col_idx, p_val)
+    grad = torch.empty_like(Y) if grad is None else grad
+    z = torch.empty(1, dtype=torch.float64, device=Y.device) if z is None else z
+    _ck(lib().hts_iteration_bh(ctx.h, _stream(stream), _ptr(Y), _ptr(update), _ptr(gains),
+                               Y.shape[0], _dtype(Y), _ptr(row_ptr), _ptr(col_idx), _ptr(p_val),
+                               float(exaggeration), tree.h, float(theta), _ptr(grad), _ptr(z),
+                               float(eta), float(momentum), float(min_gain), float(boundary_eps),
+                               int(metric_power)))
+    return grad, z
 
 
 def gradient_bh_jobs(ctx: Context, Y, row_ptr, col_idx, p_val, tree: Tree, exaggeration,
