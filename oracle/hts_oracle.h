@@ -12,6 +12,60 @@
  * double[nnz]) with columns ascending in each row and sum(val) = 1.
  *
  * Return codes: 0 ok, -1 invalid argument, -2 out of memory, -4 capacity.
+ *
+ * Pins -- what fixes each function other than itself (tests/test_oracle_*.py;
+ * a dropped term, a wrong sign or index, or a transposed operand in the
+ * function fails at least one of them):
+ *   ora_dist            closed form d(0, y) = 2 artanh|y|; symmetry and the
+ *                       triangle inequality; invariance under Mobius
+ *                       translation; the boundary example of Sec. 5
+ *                       (2 ln 19999); relative accuracy at tiny separations
+ *   ora_dist_grad       central finite differences of ora_dist; the printed
+ *                       form of eq. (13); the Euclidean limit near the origin
+ *   ora_mobius_add,     exp_y(0) = y, exp_0(v) = tanh|v| v/|v|,
+ *   ora_exp_map         d(y, exp_y v) = lambda_y |v|; Mobius identities
+ *   ora_einstein_midpoint  one point gives itself, {y, -y} gives 0, rotation
+ *                       equivariance, gyro-covariance, inside the Klein hull
+ *   ora_knn_rows        brute force (N <= 64); ties by index; any row subset
+ *                       equals the same rows of the full computation
+ *   ora_cond_p          the entropy reaches ln(perplexity) to 1e-10
+ *   ora_symmetrize,     P symmetric, non-negative, sums to 1, pattern
+ *   ora_build_affinities  kNN union its transpose
+ *   ora_kl_cost         the two-point closed form a ln a - (a - 1)(ln 2 + ln w);
+ *                       a dense sum of p ln(p / q) (N <= 64)
+ *   ora_gradient_exact  central finite differences of ora_kl_cost (the printed
+ *                       eq. (14) without the factor d fails them); Z by brute
+ *                       force; rotation covariance; the near-origin limit of
+ *                       Euclidean t-SNE (Sec. 2-B)
+ *   ora_gradient_exact_rows  all rows equal ora_gradient_exact
+ *   ora_z_exact         the brute-force sum over ordered pairs
+ *   ora_cosne_cost,     finite differences of the cost (the printed sign of
+ *   ora_cosne_gradient  the variation fails them)
+ *   ora_tree_build(_rule)  the recursive partition (ora_tree_build_partition)
+ *                       on random, duplicate-heavy and near-ray inputs; brute
+ *                       force (N <= 64); structural invariants; every point in
+ *                       one leaf; the split's sign test against exact
+ *                       rational arithmetic; points on a ray go to the upper
+ *                       half
+ *   ora_radial_mid      eq. (10) mid = (lo + hi)/2; eq. (9) against its printed
+ *                       acosh / cosh form and against equal hyperbolic areas
+ *   ora_tree_export     midpoints equal ora_einstein_midpoint of the cells;
+ *                       cell diameters by dense sampling of the cell boundary;
+ *                       the root's closed form; the shrink factor -> 1/2
+ *   ora_gradient_bh     theta = 0 equals the exact gradient and Z (also with
+ *                       duplicates); every query covers every other point
+ *                       once (sum of N_c + leaf pairs = n (n - 1)); the error
+ *                       lies in Table 3's band at theta = 0.5 and grows with
+ *                       theta
+ *   ora_gradient_bh_rows  all rows equal ora_gradient_bh, with its counters
+ *   ora_euclid_cost,    finite differences; the two-point closed form; the
+ *   ora_gradient_euclid_*  h-SNE sum against finite differences of its cost
+ *                       (the printed minus sign fails them); theta = 0 equals
+ *                       exact; cell centres of mass and diameters by brute
+ *                       force
+ *   ora_step            an independent restatement of the update rule;
+ *                       zero gradient and update keep the points; the gain
+ *                       floor; projection back into the disk; metric power 1
  */
 #ifndef HTS_ORACLE_H
 #define HTS_ORACLE_H
