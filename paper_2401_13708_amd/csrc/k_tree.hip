@@ -314,17 +314,16 @@ __global__ __launch_bounds__(kBlock) void k_sorted(const T *__restrict__ Y, int6
 }
 
 // ---------------------------------------------------------------- 5. scans
-// one block: exclusive scan of the block aggregates; writes the totals
-__global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt_part,
-                                                       DD3 *__restrict__ q_part, int64_t nb,
-                                                       int32_t *__restrict__ node_start,
-                                                       DD3 *__restrict__ psum, int64_t n,
-                                                       int32_t *__restrict__ d_m, int64_t cap,
-                                                       uint32_t *__restrict__ err) {
-    __shared__ int scnt[kBlock];
-    __shared__ DD3 sq[kBlock];
-    int64_t per = cdiv(nb, kBlock);
-    int64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+// The scan of the nb block aggregates as one workgroup takes it: thread t
+// adds blocks [t per, (t + 1) per) in order, then an inclusive Hillis-Steele
+// scan runs over the thread totals (left in scnt / sq).  Every caller gets
+// the same sums to the bit.
+__device__ __forceinline__ void parts_scan(const int32_t *__restrict__ cnt_part,
+                                           const DD3 *__restrict__ q_part, int64_t nb, int *scnt,
+                                           DD3 *sq, int64_t &b0, int64_t &b1) {
+    const int64_t per = cdiv(nb, kBlock);
+    b0 = threadIdx.x * per;
+    b1 = b0 + per < nb ? b0 + per : nb;
     int c = 0;
     DD3 v = dd_zero();
     for (int64_t b = b0; b < b1; ++b) {
@@ -334,7 +333,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt
     scnt[threadIdx.x] = c;
     sq[threadIdx.x] = v;
     __syncthreads();
-    // inclusive Hillis-Steele scan over the thread totals
     for (int o = 1; o < kBlock; o <<= 1) {
         int ca = 0;
         DD3 va = dd_zero();
@@ -350,6 +348,36 @@ __global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt
         }
         __syncthreads();
     }
+}
+
+// the totals of all blocks: node count (checked against the node storage)
+// and midpoint-summand sum
+__device__ __forceinline__ void parts_totals(const int *scnt, const DD3 *sq,
+                                             int32_t *__restrict__ node_start,
+                                             DD3 *__restrict__ psum, int64_t n,
+                                             int32_t *__restrict__ d_m, int64_t cap,
+                                             uint32_t *__restrict__ err) {
+    int m = scnt[kBlock - 1];
+    if (m > cap) {
+        atomicOr(err, HTS_ERR_TREE_OVERFLOW);
+        m = (int)cap;
+    }
+    node_start[n] = m;
+    psum[n] = sq[kBlock - 1];
+    *d_m = m;
+}
+
+// one block: exclusive scan of the block aggregates in place; writes the totals
+__global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt_part,
+                                                       DD3 *__restrict__ q_part, int64_t nb,
+                                                       int32_t *__restrict__ node_start,
+                                                       DD3 *__restrict__ psum, int64_t n,
+                                                       int32_t *__restrict__ d_m, int64_t cap,
+                                                       uint32_t *__restrict__ err) {
+    __shared__ int scnt[kBlock];
+    __shared__ DD3 sq[kBlock];
+    int64_t b0, b1;
+    parts_scan(cnt_part, q_part, nb, scnt, sq, b0, b1);
     int ex_c = threadIdx.x > 0 ? scnt[threadIdx.x - 1] : 0;
     DD3 ex_v = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd_zero();
     for (int64_t b = b0; b < b1; ++b) {
@@ -360,30 +388,54 @@ __global__ __launch_bounds__(kBlock) void k_scan_parts(int32_t *__restrict__ cnt
         ex_c += cb;
         ex_v = dd_add(ex_v, vb);
     }
-    if (threadIdx.x == kBlock - 1) {
-        int m = scnt[kBlock - 1];
-        if (m > cap) {
-            atomicOr(err, HTS_ERR_TREE_OVERFLOW);
-            m = (int)cap;
-        }
-        node_start[n] = m;
-        psum[n] = sq[kBlock - 1];
-        *d_m = m;
-    }
+    if (threadIdx.x == kBlock - 1) parts_totals(scnt, sq, node_start, psum, n, d_m, cap, err);
 }
 
 // Applies the block offsets: node_start[i] (in place of the node counts) and
 // the exclusive midpoint-summand sums; then every point records itself as the
 // first point of the nodes it starts (node_first), which are stored
-// consecutively from node_start[i].
+// consecutively from node_start[i].  With OWN, the aggregates are the raw
+// ones k_sorted left and every workgroup scans them itself as k_scan_parts
+// would (the same sums to the bit; one launch fewer, for inputs of few
+// blocks); workgroup 0 then writes the totals.
+template <bool OWN>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t *__restrict__ cnt,
                                                        DD3 *__restrict__ q, int64_t n,
                                                        const int32_t *__restrict__ cnt_part,
-                                                       const DD3 *__restrict__ q_part,
+                                                       const DD3 *__restrict__ q_part, int64_t nb,
                                                        int32_t *__restrict__ node_first,
+                                                       int32_t *__restrict__ d_m,
                                                        int64_t cap, uint32_t *__restrict__ err) {
     __shared__ int scnt[kBlock];
     __shared__ DD3 sq[kBlock];
+    __shared__ int s_bc;
+    __shared__ DD3 s_bq;
+    int32_t block_c;
+    DD3 block_q;
+    if (OWN) {
+        int64_t b0, b1;
+        parts_scan(cnt_part, q_part, nb, scnt, sq, b0, b1);
+        const int64_t me = blockIdx.x;
+        if (me >= b0 && me < b1) {  // the thread whose range holds this block
+            int c = threadIdx.x > 0 ? scnt[threadIdx.x - 1] : 0;
+            DD3 v = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd_zero();
+            for (int64_t b = b0; b < me; ++b) {
+                c += cnt_part[b];
+                v = dd_add(v, q_part[b]);
+            }
+            s_bc = c;
+            s_bq = v;
+        }
+        if (me == 0 && threadIdx.x == kBlock - 1)
+            parts_totals(scnt, sq, cnt, q, n, d_m, cap, err);  // entry n: the totals
+        __syncthreads();
+        block_c = s_bc;
+        block_q = s_bq;
+        __syncthreads();
+    } else {
+        block_c = cnt_part[blockIdx.x];
+        block_q = q_part[blockIdx.x];
+    }
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     scnt[threadIdx.x] = i < n ? cnt[i] : 0;
     sq[threadIdx.x] = i < n ? q[i] : dd_zero();
@@ -407,9 +459,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int32_t *__restrict__ cnt
         const int ex_c = threadIdx.x > 0 ? scnt[threadIdx.x - 1] : 0;
         const DD3 ex_v = threadIdx.x > 0 ? sq[threadIdx.x - 1] : dd_zero();
         const int c = scnt[threadIdx.x] - ex_c;  // nodes starting at i
-        const int32_t base = cnt_part[blockIdx.x] + ex_c;
+        const int32_t base = block_c + ex_c;
         cnt[i] = base;
-        q[i] = dd_add(q_part[blockIdx.x], ex_v);
+        q[i] = dd_add(block_q, ex_v);
         for (int a = 0; a < c; ++a) {
             const int64_t k = (int64_t)base + a;
             if (k >= cap) {  // cannot happen for a consistent scan; never write past the storage
@@ -551,6 +603,10 @@ hts_status tree_single_job(hipStream_t st, hts_tree t, int64_t n) {
     return HTS_OK;
 }
 
+// up to this many blocks (points / 256) every workgroup of the apply scans
+// the block aggregates itself
+constexpr int64_t kOwnScanBlocks = 1024;
+
 template <typename T>
 hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tree t) {
     TimedScope ts(ctx, st, HTS_K_TREE);
@@ -568,11 +624,18 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     hipLaunchKernelGGL(k_sorted<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->keys, t->perm, L,
                        (PointRec<T> *)t->spts, t->node_start, t->psum, t->ncnt_part, t->q_part);
     HTS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, st, t->ncnt_part, t->q_part, nb,
-                       t->node_start, t->psum, n, t->d_m, t->cap_nodes, ctx->d_err);
-    HTS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, st, t->node_start, t->psum, n,
-                       t->ncnt_part, t->q_part, t->node_first, t->cap_nodes, ctx->d_err);
+    if (nb <= kOwnScanBlocks) {
+        hipLaunchKernelGGL(k_scan_apply<true>, dim3(nb), dim3(kBlock), 0, st, t->node_start, t->psum,
+                           n, t->ncnt_part, t->q_part, nb, t->node_first, t->d_m, t->cap_nodes,
+                           ctx->d_err);
+    } else {
+        hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, st, t->ncnt_part, t->q_part, nb,
+                           t->node_start, t->psum, n, t->d_m, t->cap_nodes, ctx->d_err);
+        HTS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_scan_apply<false>, dim3(nb), dim3(kBlock), 0, st, t->node_start,
+                           t->psum, n, t->ncnt_part, t->q_part, nb, t->node_first, t->d_m,
+                           t->cap_nodes, ctx->d_err);
+    }
     HTS_HIP(hipGetLastError());
     // over the node capacity for n points; the kernel reads the live count
     int64_t nbm = cdiv(n * (int64_t)(L + 1) + 1, kBlock);

@@ -115,6 +115,26 @@ def test_tree_headline_size(ctx, stage):
     assert np.array_equal(g["perm"], o["perm"].astype(np.int32))
 
 
+# Sizes just past powers of two (one key in the last tile of the sort, one
+# point in the last block of the scans) and one exactly at a power of two;
+# above 262,144 points the block aggregates of the scans take a launch of
+# their own.
+@pytest.mark.parametrize("n", [131_073, 262_145, 524_288, 524_289])
+def test_tree_large_ragged_sizes(ctx, n):
+    Y = embedding(n, "late", np.float32, seed=n % 97)
+    t = hts.Tree(ctx, n, 20)
+    print("tree n=%d" % n, flush=True)
+    hts.build_polar_tree(ctx, torch.from_numpy(Y).cuda(), t)
+    g = hts.tree_export(ctx, t, n)
+    t.close()
+    assert ctx.check() == 0
+    o = oracle.Tree(Y.astype(np.float64)).export()
+    assert g["count"].size == o["count"].size
+    for key in ("count", "depth", "first", "next"):
+        assert np.array_equal(g[key], o[key]), key
+    assert np.array_equal(g["perm"], o["perm"].astype(np.int32))
+
+
 def _bh(ctx, Y, rp, col, val, theta, ex, stats=None):
     Yd = torch.from_numpy(Y).cuda()
     t = hts.Tree(ctx, Y.shape[0], 20)
