@@ -70,7 +70,11 @@ __device__ __forceinline__ PairTerm<T> pair_term(T qx, T qy, double qia, T ox, T
 // up to t^6 leave a truncation error under 2e-9, and d = (d / sinh d) sinh d.
 // Above it, d = ln(1 + t + sinh d) is well conditioned (the argument exceeds
 // 1.6), so the hardware log2 / reciprocal / square root suffice.
-template <bool QF>
+// With UNI, when every active lane takes the same branch the other one is
+// not evaluated (a wave-uniform choice; each lane's value is the same).  It
+// pays where waves are many and instruction issue bounds the kernel, and
+// costs a little where a wave's chain of dependent steps does.
+template <bool QF, bool UNI = false>
 __device__ __forceinline__ PairTerm<float> pair_term_f32(float qx, float qy, double qia, float ox,
                                                          float oy, double oib, double t,
                                                          double dq) {
@@ -82,17 +86,34 @@ __device__ __forceinline__ PairTerm<float> pair_term_f32(float qx, float qy, dou
     const float x = tf * (tf + 2.0f);
     const float rs = __builtin_amdgcn_rsqf(__builtin_fmaxf(x, 1e-30f));
     const float sh = x * rs;
-    float qs = 16.0f / 3003.0f;
-    qs = __builtin_fmaf(qs, tf, -8.0f / 693.0f);
-    qs = __builtin_fmaf(qs, tf, 8.0f / 315.0f);
-    qs = __builtin_fmaf(qs, tf, -2.0f / 35.0f);
-    qs = __builtin_fmaf(qs, tf, 2.0f / 15.0f);
-    qs = __builtin_fmaf(qs, tf, -1.0f / 3.0f);
-    qs = __builtin_fmaf(qs, tf, 1.0f);
-    const float dl = __builtin_amdgcn_logf(1.0f + tf + sh) * 0.6931471805599453f;
+    auto series = [&]() {
+        float qs = 16.0f / 3003.0f;
+        qs = __builtin_fmaf(qs, tf, -8.0f / 693.0f);
+        qs = __builtin_fmaf(qs, tf, 8.0f / 315.0f);
+        qs = __builtin_fmaf(qs, tf, -2.0f / 35.0f);
+        qs = __builtin_fmaf(qs, tf, 2.0f / 15.0f);
+        qs = __builtin_fmaf(qs, tf, -1.0f / 3.0f);
+        return __builtin_fmaf(qs, tf, 1.0f);
+    };
+    auto logd = [&]() { return __builtin_amdgcn_logf(1.0f + tf + sh) * 0.6931471805599453f; };
     const bool small = tf < 0.125f;
-    const float ratio = small ? qs : dl * rs;
-    const float d = small ? qs * sh : dl;
+    const uint64_t act = UNI ? __builtin_amdgcn_read_exec() : 1;
+    const uint64_t sm = UNI ? __builtin_amdgcn_ballot_w64(small) : 2;
+    float ratio, d;
+    if (sm == act) {
+        const float qs = series();
+        ratio = qs;
+        d = qs * sh;
+    } else if (sm == 0) {
+        const float dl = logd();
+        ratio = dl * rs;
+        d = dl;
+    } else {
+        const float qs = series();
+        const float dl = logd();
+        ratio = small ? qs : dl * rs;
+        d = small ? qs * sh : dl;
+    }
     r.w = __builtin_amdgcn_rcpf(__builtin_fmaf(d, d, 1.0f));
     r.base = QF ? ratio * (float)(4.0 * qia * oib) : ratio * (float)oib;
     // (float)(dq / 2) q = (float)dq (q / 2) exactly; q / 2 is the same for
@@ -128,17 +149,28 @@ __device__ __forceinline__ PairTerm<float> pair_term<float, false>(float qx, flo
 // The arguments dd of repel() and of arg() are what arg() hands back.
 template <int MET> struct Geo;
 
+// the repulsive term's pair: no query factor, and for single precision the
+// wave-uniform branch choice as asked
+template <typename T, bool UNI>
+__device__ __forceinline__ PairTerm<T> rep_term(T qx, T qy, double qia, T ox, T oy, double oib,
+                                                double t, double dq) {
+    if constexpr (sizeof(T) == 4)
+        return pair_term_f32<false, UNI>(qx, qy, qia, ox, oy, oib, t, dq);
+    else
+        return pair_term<T, false>(qx, qy, qia, ox, oy, oib, t, dq);
+}
+
 template <> struct Geo<0> {
     template <typename T>
     static __device__ __forceinline__ double arg(const PointRec<T> &me, T ox, T oy, double oib,
                                                  double &dd) {
         return dist_arg<T>(me.x, me.y, me.ia, ox, oy, oib, dd);
     }
-    template <typename T, typename Z>
+    template <bool UNI = false, typename T, typename Z>
     static __device__ __forceinline__ void repel(const PointRec<T> &me, T ox, T oy, double oib,
                                                  double t, double dd, T weight, T &fx, T &fy,
                                                  Z &z) {
-        const PairTerm<T> r = pair_term<T, false>(me.x, me.y, me.ia, ox, oy, oib, t, dd);
+        const PairTerm<T> r = rep_term<T, UNI>(me.x, me.y, me.ia, ox, oy, oib, t, dd);
         const T coef = weight * r.w * r.w * r.base;
         fx += coef * r.vx;
         fy += coef * r.vy;
@@ -176,7 +208,7 @@ template <> struct Geo<1> {
         dd = dx * dx + dy * dy;
         return dd;
     }
-    template <typename T, typename Z>
+    template <bool UNI = false, typename T, typename Z>
     static __device__ __forceinline__ void repel(const PointRec<T> &me, T ox, T oy, double oib,
                                                  double t, double dd, T weight, T &fx, T &fy,
                                                  Z &z) {

@@ -9,8 +9,8 @@
 // distance argument t in double) and adds N_cell w^2 d dd/dy, or joins the
 // set of lanes that need the children.  Leaves are evaluated exactly, skipping
 // the query.  The lanes that need a subtree form a 64-bit mask per depth, kept
-// in two VGPRs used as lane-indexed arrays (readlane with the depth to read,
-// a lane select to write), and a mask serves directly as the lane predicate
+// in two VGPRs used as lane-indexed arrays (readlane and writelane with the
+// depth as the lane), and a mask serves directly as the lane predicate
 // of the masked term.  Node records are read with scalar loads; the next
 // sibling's is in flight while a node is evaluated, and so is the first
 // child's in the walks of the work items (phase A loads it when it descends);
@@ -65,6 +65,18 @@ struct alignas(16) ItemRec {
     uint64_t pad;
 };
 
+// lane l of (lo, hi) set to the two halves of x (x and l uniform;
+// v_writelane ignores the execution mask).  The lane select goes through m0
+// (one scalar source besides m0 per vector instruction), with a wait state
+// after writing it.
+__device__ __forceinline__ void write_lanes(int &lo, int &hi, uint64_t x, int l) {
+    asm volatile("s_mov_b32 m0, %4\n\ts_nop 0\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
+                 : "+v"(lo), "+v"(hi)
+                 : "s"(uniform((int)(uint32_t)x)), "s"(uniform((int)(uint32_t)(x >> 32))),
+                   "s"(uniform(l))
+                 : "m0");
+}
+
 struct Counters {
     unsigned long long test = 0, acc = 0, pair = 0, step = 0, work = 0, cover = 0;
 };
@@ -80,7 +92,12 @@ struct Counters {
 // successor index is at most M, and the node arrays hold more than M records
 // (their capacity n_max (depth cap + 1) + 1 exceeds any node count), so the
 // successor of the last node is a readable record that is never used.
-template <typename T, int MET, bool STATS, bool EMIT>
+// THRU marks the walks of phase B, which run among many waves and are bound
+// by instruction issue: there scalar branches that save vector instructions
+// pay (the term's wave-uniform branch choice, and the mask of the current
+// depth kept in scalar registers and read from the stack only when the walk
+// moves up); in phase A, a chain of dependent steps, they would lengthen it.
+template <typename T, int MET, bool STATS, bool EMIT, bool THRU = false>
 __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M,
                                      const PointRec<T> *__restrict__ spts, const PointRec<T> &me,
                                      int64_t q, int lane, int k, int kend, int d0, uint64_t mask0,
@@ -89,6 +106,19 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
     T zw = 0;  // this walk's Z terms, added to z once at the end
     int mlo = lane == d0 ? (int)(uint32_t)mask0 : 0;
     int mhi = lane == d0 ? (int)(uint32_t)(mask0 >> 32) : 0;
+    // with THRU, the mask of depth mdep (equal to its stack entry)
+    uint64_t mc = mask0;
+    int mdep = d0;
+    auto mask_at = [&](int depth) -> uint64_t {
+        if (THRU && depth == mdep) return mc;
+        const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
+                           (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
+        if (THRU) {
+            mc = m;
+            mdep = depth;
+        }
+        return m;
+    };
     NodeRec<T> nrec = nodes[k < M ? k : M - 1];
     while (k < kend) {
         NodeRec<T> cur = nrec;
@@ -100,8 +130,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
         bool inner = next != k + 1;
         while (inner) {
             const int depth = (int)(nxd >> kNextBits);
-            const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
-                               (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
+            const uint64_t m = mask_at(depth);
             // the next sibling's record is loaded before the test and the term
             // (the compiler barrier keeps the load from sinking to its use);
             // the first child's too in the walks that emit no items, and only
@@ -119,7 +148,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             const double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
             const uint64_t am = __builtin_amdgcn_ballot_w64(t > cur.c) & m;
             if (__builtin_amdgcn_inverse_ballot_w64(am))
-                Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, zw);
+                Geo<MET>::template repel<THRU>(me, cur.mx, cur.my, cur.ib, t, dd, (T)cur.count, fx, fy, zw);
             const uint64_t rej = m & ~am;
             if (STATS) {
                 c.test += __popcll(m);
@@ -133,9 +162,11 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 k = next;
                 nrec = over;
             } else if (rej) {
-                const bool here = lane == depth + 1;
-                mlo = here ? (int)(uint32_t)rej : mlo;
-                mhi = here ? (int)(uint32_t)(rej >> 32) : mhi;
+                write_lanes(mlo, mhi, rej, depth + 1);
+                if (THRU) {
+                    mc = rej;
+                    mdep = depth + 1;
+                }
                 nrec = !EMIT ? first_child : nodes[(uint32_t)(k + 1)];
                 k = k + 1;
             } else {
@@ -150,8 +181,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
         if (k >= kend) break;
         // leaf: exact terms with each of its points, skipping the query
         const int depth = (int)(nxd >> kNextBits);
-        const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, depth) << 32) |
-                           (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, depth);
+        const uint64_t m = mask_at(depth);
         const bool in = __builtin_amdgcn_inverse_ballot_w64(m);
         const NodeRec<T> over = nodes[(uint32_t)next];
         if (STATS) c.step += 1;
@@ -162,7 +192,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
             if (use) {
                 double dd;
                 double t = Geo<MET>::arg(me, cur.mx, cur.my, cur.ib, dd);
-                Geo<MET>::repel(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, zw);
+                Geo<MET>::template repel<THRU>(me, cur.mx, cur.my, cur.ib, t, dd, (T)1, fx, fy, zw);
             }
             if (STATS) {
                 const uint64_t um = __ballot(use);
@@ -177,7 +207,7 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 if (use) {
                     double dd;
                     double t = Geo<MET>::arg(me, o.x, o.y, o.ia, dd);
-                    Geo<MET>::repel(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, zw);
+                    Geo<MET>::template repel<THRU>(me, o.x, o.y, o.ia, t, dd, (T)1, fx, fy, zw);
                 }
                 if (STATS) {
                     const int u = __popcll(__ballot(use));
@@ -413,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
         T fx = 0, fy = 0;
         double z = 0.0;
         Counters c;
-        walk<T, MET, STATS, false>(nodes, M, spts, me, q, lane, rec.node + 1,
+        walk<T, MET, STATS, false, true>(nodes, M, spts, me, q, lane, rec.node + 1,
                                    (int)(rec.nd & kNextMask), (int)(rec.nd >> kNextBits) + 1,
                                    rec.mask, 0, nullptr, dummy, fx, fy, z, c);
         if (valid) {
