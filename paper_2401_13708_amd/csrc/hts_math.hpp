@@ -312,17 +312,16 @@ __device__ __forceinline__ DD3 dd_zero() {
 }
 
 // ---------------------------------------------------------------- attraction
-// First sum of eq. (15) for the rows of one workgroup of kBlock threads:
-// F_attr,i = sum_{j in row i} p_ij w_ij d_ij dd_ij/dy_i.  G lanes share a CSR
-// row; column/value reads are contiguous per row, the point records of the
-// columns are gathered (they stay in L2).
+// First sum of eq. (15), F_attr,i = sum_{j in row i} p_ij w_ij d_ij dd_ij/dy_i,
+// by thread gid of a grid of G threads per row (groups of G lanes aligned in
+// a wave): column/value reads are contiguous per row, the point records of
+// the columns are gathered (they stay in L2).
 template <typename T, int G, int MET = 0>
-__device__ __forceinline__ void attract_rows(int64_t block, const PointRec<T> *__restrict__ pts,
+__device__ __forceinline__ void attract_rows(int64_t gid, const PointRec<T> *__restrict__ pts,
                                              const int64_t *__restrict__ rp,
                                              const int32_t *__restrict__ col,
                                              const T *__restrict__ val, int64_t n,
                                              T *__restrict__ fattr, uint32_t *__restrict__ err) {
-    const int64_t gid = block * kBlock + threadIdx.x;
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     T fx = 0, fy = 0;

@@ -242,27 +242,17 @@ __device__ __forceinline__ void put_stats(uint32_t *__restrict__ sp, const Count
 // rejected ancestor becomes a work item, leaves the walk -- then walks f's
 // subtree.  An ancestor's term, item and counters belong to the one slot whose
 // digits below it are all 0, so every lane meets every cell exactly as in a
-// single depth-first walk.  These waves are latency-bound chains and leave
-// most of the chip idle, so the same launch also carries the attractive term
-// (first sum of eq. (15)), which streams P: workgroups from top_blocks on
-// compute its rows.
+// single depth-first walk.  These waves are latency-bound chains; nothing
+// else shares their launch (the attractive rows, which compete with them for
+// vector issue, run at the end of phase B's).
 template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_top(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
     const int32_t *__restrict__ node_start, Jobs jb, const PointRec<T> *__restrict__ spts,
     int64_t nqb, int S, int *__restrict__ item_base, int *__restrict__ nitems_out,
     T *__restrict__ part0, double *__restrict__ ztop, uint32_t *__restrict__ stats_top,
-    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense, int share,
-    int64_t top_blocks,
-    const PointRec<T> *__restrict__ pts, const int64_t *__restrict__ rp,
-    const int32_t *__restrict__ col, const T *__restrict__ val, int64_t n, T *__restrict__ fattr,
-    uint32_t *__restrict__ err) {
+    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense, int share, int64_t n) {
     __shared__ LdsItem s_items[kBlock / kWave][kItemCap];
-    if ((int64_t)blockIdx.x >= top_blocks) {
-        attract_rows<T, kAttractLanes, MET>((int64_t)blockIdx.x - top_blocks, pts, rp, col, val,
-                                            n, fattr, err);
-        return;
-    }
     const int64_t g = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     const int64_t qb = g / kTopSlots;
     const int slot = (int)(g % kTopSlots);
@@ -427,13 +417,23 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
     const PointRec<T> *__restrict__ spts, const unsigned *__restrict__ dense_count,
     const ItemRec *__restrict__ dense, int64_t cap, T *__restrict__ part,
-    double *__restrict__ zitem, uint32_t *__restrict__ stats_items) {
+    double *__restrict__ zitem, uint32_t *__restrict__ stats_items, int64_t item_blocks,
+    const PointRec<T> *__restrict__ pts, const int64_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const T *__restrict__ val, int64_t n, T *__restrict__ fattr,
+    uint32_t *__restrict__ err) {
+    // the workgroups past the items' compute the attractive rows: they start
+    // last, and fill the chip while the longest walks finish
+    if ((int64_t)blockIdx.x >= item_blocks) {
+        attract_rows<T, kAttractLanes, MET>(((int64_t)blockIdx.x - item_blocks) * blockDim.x +
+                                                threadIdx.x, pts, rp, col, val, n, fattr, err);
+        return;
+    }
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int M = uniform(*d_m);
     const int64_t reserved = (int64_t)(uint32_t)uniform((int)*dense_count);
     const int64_t total = reserved < cap ? reserved : cap;  // never more, by the shares
     const int wpb = (int)(blockDim.x / kWave);
-    const int64_t G = (int64_t)gridDim.x * wpb;
+    const int64_t G = item_blocks * wpb;
     int dummy = 0;
     for (int64_t i = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; i < total; i += G) {
         const ItemRec rec = load_item(dense, i);
@@ -681,26 +681,27 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     {
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
         const int64_t top_blocks = cdiv(nw, kBlock / kWave);
-        const dim3 ga(top_blocks + cdiv(n * kAttractLanes, kBlock));
+        const dim3 ga(top_blocks);
         if (stats)
             hipLaunchKernelGGL((k_bh_top<T, MET, true>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
-                               st_top, dense_count, dense, share, top_blocks, pts, rp, col, val, n, fattr,
-                               ctx->d_err);
+                               st_top, dense_count, dense, share, n);
         else
             hipLaunchKernelGGL((k_bh_top<T, MET, false>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
-                               nullptr, dense_count, dense, share, top_blocks, pts, rp, col, val, n,
-                               fattr, ctx->d_err);
+                               nullptr, dense_count, dense, share, n);
     }
     {
         TimedScope ts(ctx, st, HTS_K_ITEMS);
+        const dim3 gb(gi + cdiv(n * kAttractLanes, wpb * kWave));
         if (stats)
-            hipLaunchKernelGGL((k_bh_items<T, MET, true>), dim3(gi), dim3(wpb * kWave), 0, st, nodes, t->d_m,
-                               spts, dense_count, dense, slots, part, zitem, st_items);
+            hipLaunchKernelGGL((k_bh_items<T, MET, true>), gb, dim3(wpb * kWave), 0, st, nodes, t->d_m,
+                               spts, dense_count, dense, slots, part, zitem, st_items, gi, pts, rp,
+                               col, val, n, fattr, ctx->d_err);
         else
-            hipLaunchKernelGGL((k_bh_items<T, MET, false>), dim3(gi), dim3(wpb * kWave), 0, st, nodes,
-                               t->d_m, spts, dense_count, dense, slots, part, zitem, nullptr);
+            hipLaunchKernelGGL((k_bh_items<T, MET, false>), gb, dim3(wpb * kWave), 0, st, nodes,
+                               t->d_m, spts, dense_count, dense, slots, part, zitem, nullptr, gi, pts,
+                               rp, col, val, n, fattr, ctx->d_err);
     }
     HTS_HIP(hipGetLastError());
     TimedScope ts(ctx, st, HTS_K_FINALIZE);

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_attract(const PointRec<T> *__restric
                                                     const T *__restrict__ val, int64_t n,
                                                     T *__restrict__ fattr,
                                                     uint32_t *__restrict__ err) {
-    attract_rows<T, G>(blockIdx.x, pts, rp, col, val, n, fattr, err);
+    attract_rows<T, G>((int64_t)blockIdx.x * kBlock + threadIdx.x, pts, rp, col, val, n, fattr, err);
 }
 
 template <typename T>
