@@ -44,6 +44,10 @@ F_TEST, F_PAIR = 9, 26
 # compares (6 flops); an interaction adds w = 1/(1+|y-c|^2), N w^2, the
 # direction vector and the three accumulations (12 flops).
 F_TEST_E, F_PAIR_E = 6, 12
+# The attractive term, which the launch of the traversal's second kernel also
+# computes: per non-zero of P the distance argument (a test without its
+# compare) and the pair term without the Z accumulation.
+F_ATTR, F_ATTR_E = (F_TEST - 1) + (F_PAIR - 2), (F_TEST_E - 1) + (F_PAIR_E - 2)
 METRIC_HSNE = "h-SNE BH gradient iters/sec at N=70k θ=0.5 (Euclidean + λ hyperbolic term)"
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 # iterations of the 1000-iteration schedule where the timed windows start
@@ -650,7 +654,7 @@ def bench_single(args):
 
     # roofline of the dominant kernel of the timed windows
     names = {"tree": "tree build", "attract": "k_attract",
-             "traverse": "k_bh_top (with the attractive rows)", "items": "k_bh_items",
+             "traverse": "k_bh_top", "items": "k_bh_items (with the attractive rows)",
              "finalize": "k_bh_gather + k_bh_finalize", "step": "k_step"}
     kms = {c: v[0] for c, v in kt_tot.items()}
     launches = {c: v[1] for c, v in kt_tot.items()}
@@ -661,13 +665,21 @@ def bench_single(args):
         if dom in ("traverse", "items") and not args.no_stats:
             def part(c):  # the kernel's share of one traversal's counters
                 return c[K:2 * K] if dom == "items" else [a - b for a, b in zip(c[:K], c[K:2 * K])]
+            # the counting pass covers the same windows as the timed launches,
+            # one traversal (two for h-SNE) per timed iteration
+            iters = sum(k for _, k in windows)
             if hs is None:
                 sh = part(st_tot[:2 * K])
-                flops = (sh[0] * F_TEST + (sh[1] + sh[2]) * F_PAIR) / launches[dom]
+                flops = sh[0] * F_TEST + (sh[1] + sh[2]) * F_PAIR
+                if dom == "items":
+                    flops += iters * nnz * F_ATTR
             else:  # two launches per iteration: the Euclidean walk, then the hyperbolic one
                 se, sh = part(st_tot[:2 * K]), part(st_tot[2 * K:4 * K])
                 flops = (se[0] * F_TEST_E + (se[1] + se[2]) * F_PAIR_E + sh[0] * F_TEST
-                         + (sh[1] + sh[2]) * F_PAIR) / launches[dom]
+                         + (sh[1] + sh[2]) * F_PAIR)
+                if dom == "items":
+                    flops += iters * nnz * (F_ATTR_E + F_ATTR)
+            flops /= launches[dom]
             ach = flops / avg_s / 1e12
             roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),
