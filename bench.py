@@ -253,11 +253,16 @@ def bench_jobs(args):
     print("bench: %d jobs, %d points in all, set up in %.1fs" % (len(jobs), total_n, setup_s),
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    (best, best_launch), table = autotune_traversal(ctx, jobs, theta=args.theta)
+    (best, best_launch, best_attract), table = autotune_traversal(ctx, jobs, theta=args.theta)
     tune_s = time.perf_counter() - t0
     print("bench: work-item size %d (ms/iteration %s)" % (best, {k: round(v, 3) for k, v in table.items()}),
           file=sys.stderr, flush=True)
-    # one job at a time through the single-job calls
+    # one job at a time through the single-job calls, with the tuned work-item
+    # size (the same sums as the batched runs) and the library's default
+    # launch shapes (the tuned ones are for the whole layout; they change
+    # nothing in the result)
+    ctx.set_traversal_launch(hts.DEFAULT_ITEMS_GRID, hts.DEFAULT_ITEMS_WAVES)
+    ctx.set_attract_launch(hts.DEFAULT_ATTRACT_LAUNCH)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     finals = []
@@ -268,6 +273,8 @@ def bench_jobs(args):
         e.close()
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
+    ctx.set_traversal_launch(*best_launch)
+    ctx.set_attract_launch(best_attract)
     print("bench: sequential %.2fs" % t_seq, file=sys.stderr, flush=True)
     # all jobs in one layout
     torch.cuda.synchronize()
@@ -311,6 +318,7 @@ def bench_jobs(args):
         "speedup_vs_sequential": round(t_seq / t_graph, 2),
         "max_abs_diff_vs_sequential": max(diff, diff_g),
         "autotune": {"item_points": best, "traversal_launch": list(best_launch),
+                     "attract_launch": best_attract,
                      "ms_per_iteration": {str(k): round(v, 4) for k, v in table.items()},
                      "tune_s": round(tune_s, 2)},
         "setup_s": round(setup_s, 2),
@@ -434,6 +442,8 @@ def bench_single(args):
     if args.items_grid is not None or args.items_waves is not None:
         ctx.set_traversal_launch(args.items_grid or hts.DEFAULT_ITEMS_GRID,
                                  args.items_waves or hts.DEFAULT_ITEMS_WAVES)
+    if args.attract_launch is not None:
+        ctx.set_attract_launch(args.attract_launch)
     Xd = torch.from_numpy(X).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -748,6 +758,7 @@ def bench_single(args):
                    "split_rule": "equal lengths, eq. (10)" if args.split_rule == 0
                    else "equal areas, eq. (9)", "hsne_lambda": hs, "item_list": ctx.item_list,
                    "item_points": ctx.item_points, "traversal_launch": list(ctx.traversal_launch),
+                   "attract_launch": ctx.attract_launch,
                    "windows": windows},
         "windows": win_out,
         "exact_iters_per_s": round(exact_ips, 3) if exact_ips else None,
@@ -922,6 +933,9 @@ def main():
                          "workgroups per first-kernel wave)")
     ap.add_argument("--items-waves", type=int, default=None,
                     help="waves per workgroup of that kernel: 1, 2 or 4 (library default 1)")
+    ap.add_argument("--attract-launch", type=int, choices=[0, 1, 2], default=None,
+                    help="launch of the attractive term: 0 automatic (library default), 1 beside "
+                         "phase A, 2 at the end of phase B")
     ap.add_argument("--item-list", type=int, default=None,
                     help="item-list entries per phase-A wave (library default 256)")
     ap.add_argument("--hsne-lambda", type=float, default=None,

@@ -332,6 +332,17 @@ hts_status hts_set_item_list(hts_ctx ctx, int32_t items_per_wave);
  * all (bit for bit).  Applies to later calls on ctx. */
 hts_status hts_set_traversal_launch(hts_ctx ctx, int32_t workgroups, int32_t waves_per_workgroup);
 
+/* Where the Barnes-Hut gradient computes its attractive term (the first sum
+ * of eq. (15)): 1 in the traversal's first launch, beside the walks of the
+ * large cells (its waves then compete with those chains for issue, and are
+ * hidden when the chains are long), 2 in the last workgroups of the second
+ * launch (they start after the work items and fill the chip while the longest
+ * walks finish), 0 automatic (1 when the largest job of the tree's layout has
+ * at least 131072 points, else 2).  The result does not depend on the choice
+ * (bit for bit).  HTS_EINVAL for another value or a NULL ctx.  Applies to
+ * later calls on ctx. */
+hts_status hts_set_attract_launch(hts_ctx ctx, int32_t where);
+
 /* Workspace generation of ctx (host, *gen_out).  The context keeps device
  * workspaces that grow on demand, and a job layout (hts_tree_set_jobs)
  * replaces its tree's tables; either reallocation changes this counter.

@@ -160,6 +160,17 @@ class JobBatch:
             self.tree = None
 
 
+def pick_setting(times: dict, default, margin: float):
+    """The fastest of the timed settings ({setting: ms}), or `default` unless
+    the fastest beats it by more than the fraction `margin`."""
+    if not times:
+        return default
+    best = min(times, key=times.get)
+    if default in times and times[best] > (1.0 - margin) * times[default]:
+        return default
+    return best
+
+
 # launch shapes of the traversal's second kernel: (workgroups, waves per workgroup)
 TRAVERSAL_LAUNCHES = ((0, 1), (16384, 4), (65536, 2), (32768, 1), (65536, 1), (131072, 1),
                       (262144, 1))
@@ -167,21 +178,27 @@ TRAVERSAL_LAUNCHES = ((0, 1), (16384, 4), (65536, 2), (32768, 1), (65536, 1), (1
 
 def autotune_traversal(ctx: hts.Context, jobs: list[Job], candidates=(128, 256, 512, 1024, 2048),
                        launches=TRAVERSAL_LAUNCHES, warm: int = 100, reps: int = 8,
-                       theta: float = 0.5) -> tuple[tuple[int, tuple[int, int]], dict]:
+                       theta: float = 0.5, margin: float = 0.02
+                       ) -> tuple[tuple[int, tuple[int, int], int], dict]:
     """Picks the Barnes-Hut traversal's tile and launch shapes for a batch of
     jobs by timing: the work-item size S (the walks handed to the second
     kernel hold at most S points), then, at the best S, the second kernel's
-    workgroup count (0: the library's automatic count) and waves per workgroup.
+    workgroup count (0: the library's automatic count) and waves per
+    workgroup, then the launch that computes the attractive term (0:
+    automatic, 1: beside phase A, 2: at the end of phase B).
 
     A scratch copy of the batch is advanced `warm` iterations (the embedding
     spreads out, which changes the traversal), then every candidate times
     `reps` iterations from that same state.  The fastest setting is left on
     ctx and returned with the milliseconds per iteration of every candidate
-    ({"S=..": ms, "grid=..x..": ms}).  S changes only the order of
-    floating-point sums; the launch shape changes nothing in the result."""
+    ({"S=..": ms, "grid=..x..": ms, "attract=..": ms}); a setting replaces the library's
+    default only when it is faster by more than `margin` (a fraction), so
+    that timing noise does not pick it.  S changes only the order of
+    floating-point sums; the launch shapes change nothing in the result."""
     b = JobBatch(ctx, jobs, theta=theta)
     ctx.set_item_points(hts.DEFAULT_ITEM_POINTS)
     ctx.set_traversal_launch(hts.DEFAULT_ITEMS_GRID, hts.DEFAULT_ITEMS_WAVES)
+    ctx.set_attract_launch(hts.DEFAULT_ATTRACT_LAUNCH)
     b.run(warm)
     saved = [t.clone() for t in (b.Y, b.update, b.gains, b.it)]
 
@@ -202,13 +219,19 @@ def autotune_traversal(ctx: hts.Context, jobs: list[Job], candidates=(128, 256, 
     for S in candidates:
         ctx.set_item_points(S)
         by_s[S] = times["S=%d" % S] = timed()
-    best_s = min(by_s, key=by_s.get) if by_s else hts.DEFAULT_ITEM_POINTS
+    best_s = pick_setting(by_s, hts.DEFAULT_ITEM_POINTS, margin)
     ctx.set_item_points(best_s)
     by_l = {}
     for g, w in launches:
         ctx.set_traversal_launch(g, w)
         by_l[(g, w)] = times["grid=%dx%d" % (g, w)] = timed()
-    best_l = min(by_l, key=by_l.get) if by_l else (hts.DEFAULT_ITEMS_GRID, hts.DEFAULT_ITEMS_WAVES)
+    best_l = pick_setting(by_l, (hts.DEFAULT_ITEMS_GRID, hts.DEFAULT_ITEMS_WAVES), margin)
     ctx.set_traversal_launch(*best_l)
+    by_a = {}
+    for where in (0, 1, 2):
+        ctx.set_attract_launch(where)
+        by_a[where] = times["attract=%d" % where] = timed()
+    best_a = pick_setting(by_a, hts.DEFAULT_ATTRACT_LAUNCH, margin)
+    ctx.set_attract_launch(best_a)
     b.close()
-    return (best_s, best_l), times
+    return (best_s, best_l, best_a), times

@@ -308,6 +308,9 @@ hts_status hts_tree_set_jobs(hts_tree t, int32_t n_jobs, const int64_t *n_per_jo
     HTS_HIP(hipMemcpy(t->pjob, pj.data(), pj.size() * 4, hipMemcpyHostToDevice));
     t->J = n_jobs;
     t->h_off = off;
+    t->max_job = 0;
+    for (int32_t j = 0; j < n_jobs; ++j)
+        if (off[j + 1] - off[j] > t->max_job) t->max_job = off[j + 1] - off[j];
     t->nqb = nqb;
     t->jobs_set = true;
     t->tab_n = n;
@@ -758,6 +761,14 @@ hts_status hts_set_traversal_launch(hts_ctx c, int32_t workgroups, int32_t waves
         return fail(HTS_EINVAL, "hts_set_traversal_launch: waves_per_workgroup must be 1, 2 or 4");
     c->items_grid = workgroups;
     c->items_waves = waves_per_workgroup;
+    return HTS_OK;
+}
+
+hts_status hts_set_attract_launch(hts_ctx c, int32_t where) {
+    if (!c) return fail(HTS_EINVAL, "hts_set_attract_launch: ctx is NULL");
+    if (where < 0 || where > 2)
+        return fail(HTS_EINVAL, "hts_set_attract_launch: where = %d not 0 (automatic), 1 or 2", where);
+    c->attract_at = where;
     return HTS_OK;
 }
 

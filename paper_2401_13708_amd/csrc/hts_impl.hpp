@@ -98,6 +98,7 @@ struct hts_ctx_s {
     int32_t list_items = 256;   // item-list entries per phase-A wave (hts_set_item_list)
     int32_t items_grid = 0;     // phase-B workgroups at most, 0: automatic (hts_set_traversal_launch)
     int32_t items_waves = 1;    // waves per phase-B workgroup
+    int32_t attract_at = 0;     // attractive rows: 0 automatic, 1 phase A, 2 phase B (hts_set_attract_launch)
     uint32_t *d_err = nullptr;
     // changes whenever device memory that launches on this context referenced
     // is reallocated (a workspace grown, a job layout's tables replaced)
@@ -122,6 +123,7 @@ struct hts_tree_s {
     bool jobs_set = false;        // layout given by hts_tree_set_jobs
     int64_t tab_n = -1;           // n the single-job tables were written for
     std::vector<int64_t> h_off;   // host copy of off
+    int64_t max_job = 0;          // points of the largest job of the layout
     int64_t *job_off = nullptr;   // [J+1]
     int32_t *job_qb = nullptr;    // [J+1] first query block of each job
     int32_t *qb_job = nullptr;    // [nqb_max] job of each query block

@@ -42,6 +42,7 @@ namespace hts {
 
 constexpr int kStats = kBhStats;
 constexpr int kAttractLanes = 16;  // lanes per CSR row of the attractive term
+constexpr int64_t kAttractWithTopAt = 131072;  // automatic placement threshold (points of a job)
 constexpr int kItemCap = 256;  // items one phase-A wave can hand to phase B
 // The item list holds ctx->list_items items per phase-A wave (kItemCap by
 // default: every item a wave records); a wave hands over at most that many
@@ -242,17 +243,27 @@ __device__ __forceinline__ void put_stats(uint32_t *__restrict__ sp, const Count
 // rejected ancestor becomes a work item, leaves the walk -- then walks f's
 // subtree.  An ancestor's term, item and counters belong to the one slot whose
 // digits below it are all 0, so every lane meets every cell exactly as in a
-// single depth-first walk.  These waves are latency-bound chains; nothing
-// else shares their launch (the attractive rows, which compete with them for
-// vector issue, run at the end of phase B's).
+// single depth-first walk.  These waves are latency-bound chains.  The
+// attractive term (first sum of eq. (15)) runs either in this launch, in the
+// workgroups from top_blocks on, where its waves compete with the chains for
+// issue and are hidden when the chains are long, or in the last workgroups of
+// phase B's launch (hts_set_attract_launch).
 template <typename T, int MET, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_bh_top(
     const NodeRec<T> *__restrict__ nodes, const int32_t *__restrict__ d_m,
     const int32_t *__restrict__ node_start, Jobs jb, const PointRec<T> *__restrict__ spts,
     int64_t nqb, int S, int *__restrict__ item_base, int *__restrict__ nitems_out,
     T *__restrict__ part0, double *__restrict__ ztop, uint32_t *__restrict__ stats_top,
-    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense, int share, int64_t n) {
+    unsigned *__restrict__ dense_count, ItemRec *__restrict__ dense, int share, int64_t n,
+    int64_t top_blocks, const PointRec<T> *__restrict__ pts, const int64_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const T *__restrict__ val, T *__restrict__ fattr,
+    uint32_t *__restrict__ err) {
     __shared__ LdsItem s_items[kBlock / kWave][kItemCap];
+    if ((int64_t)blockIdx.x >= top_blocks) {
+        attract_rows<T, kAttractLanes, MET>(((int64_t)blockIdx.x - top_blocks) * kBlock + threadIdx.x,
+                                            pts, rp, col, val, n, fattr, err);
+        return;
+    }
     const int64_t g = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     const int64_t qb = g / kTopSlots;
     const int slot = (int)(g % kTopSlots);
@@ -421,8 +432,9 @@ __global__ __launch_bounds__(kBlock) void k_bh_items(
     const PointRec<T> *__restrict__ pts, const int64_t *__restrict__ rp,
     const int32_t *__restrict__ col, const T *__restrict__ val, int64_t n, T *__restrict__ fattr,
     uint32_t *__restrict__ err) {
-    // the workgroups past the items' compute the attractive rows: they start
-    // last, and fill the chip while the longest walks finish
+    // the workgroups past the items' compute the attractive rows when they
+    // run here: they start last, and fill the chip while the longest walks
+    // finish
     if ((int64_t)blockIdx.x >= item_blocks) {
         attract_rows<T, kAttractLanes, MET>(((int64_t)blockIdx.x - item_blocks) * blockDim.x +
                                                 threadIdx.x, pts, rp, col, val, n, fattr, err);
@@ -670,6 +682,10 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     // waves per phase-A wave (about one per item: the hardware hands each
     // freed wave slot the next item), never more than the list holds
     const int wpb = ctx->items_waves;
+    // the attractive rows beside phase A (long chains hide them) or at the end
+    // of phase B; automatic: beside phase A for a job of 131072 points or more
+    const int64_t largest = t->jobs_set ? t->max_job : n;
+    const bool attract_a = ctx->attract_at == 1 || (ctx->attract_at == 0 && largest >= kAttractWithTopAt);
     int64_t gi = ctx->items_grid > 0 ? (int64_t)ctx->items_grid : cdiv(32 * nw, wpb);
     if (gi > cdiv(slots, wpb)) gi = cdiv(slots, wpb);
     if (gi < 1) gi = 1;          // an empty list (no items can be handed over)
@@ -681,19 +697,21 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     {
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
         const int64_t top_blocks = cdiv(nw, kBlock / kWave);
-        const dim3 ga(top_blocks);
+        const dim3 ga(top_blocks + (attract_a ? cdiv(n * kAttractLanes, kBlock) : 0));
         if (stats)
             hipLaunchKernelGGL((k_bh_top<T, MET, true>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
-                               st_top, dense_count, dense, share, n);
+                               st_top, dense_count, dense, share, n, top_blocks, pts, rp, col,
+                               val, fattr, ctx->d_err);
         else
             hipLaunchKernelGGL((k_bh_top<T, MET, false>), ga, dim3(kBlock), 0, st, nodes, t->d_m,
                                t->node_start, jb, spts, nqb, S, item_base, nitems, part0, ztop,
-                               nullptr, dense_count, dense, share, n);
+                               nullptr, dense_count, dense, share, n, top_blocks, pts, rp, col,
+                               val, fattr, ctx->d_err);
     }
     {
         TimedScope ts(ctx, st, HTS_K_ITEMS);
-        const dim3 gb(gi + cdiv(n * kAttractLanes, wpb * kWave));
+        const dim3 gb(gi + (attract_a ? 0 : cdiv(n * kAttractLanes, wpb * kWave)));
         if (stats)
             hipLaunchKernelGGL((k_bh_items<T, MET, true>), gb, dim3(wpb * kWave), 0, st, nodes, t->d_m,
                                spts, dense_count, dense, slots, part, zitem, st_items, gi, pts, rp,

@@ -61,6 +61,7 @@ _SIGS = {
     "hts_set_item_points": (C.c_int, [_P, _I32]),
     "hts_set_item_list": (C.c_int, [_P, _I32]),
     "hts_set_traversal_launch": (C.c_int, [_P, _I32, _I32]),
+    "hts_set_attract_launch": (C.c_int, [_P, _I32]),
     "hts_cosne_terms": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _D, _D, _P]),
     "hts_tree_set_split": (C.c_int, [_P, _I32]),
     "hts_workspace_generation": (C.c_int, [_P, C.POINTER(C.c_uint64)]),
@@ -136,6 +137,7 @@ DEFAULT_ITEM_POINTS = 256  # the library's default work-item size
 DEFAULT_ITEM_LIST = 256    # the library's default item-list entries per phase-A wave
 DEFAULT_ITEMS_GRID = 0     # the library's default phase-B workgroups (0: automatic) ...
 DEFAULT_ITEMS_WAVES = 1    # ... of this many waves
+DEFAULT_ATTRACT_LAUNCH = 0  # the attractive rows' launch: 0 automatic, 1 phase A, 2 phase B
 
 
 class Context:
@@ -149,6 +151,7 @@ class Context:
         self.item_points = DEFAULT_ITEM_POINTS
         self.item_list = DEFAULT_ITEM_LIST
         self.traversal_launch = (DEFAULT_ITEMS_GRID, DEFAULT_ITEMS_WAVES)
+        self.attract_launch = DEFAULT_ATTRACT_LAUNCH
 
     def close(self):
         if getattr(self, "h", None):
@@ -179,6 +182,13 @@ class Context:
         the result does not depend on it)."""
         _ck(lib().hts_set_traversal_launch(self.h, int(workgroups), int(waves_per_workgroup)))
         self.traversal_launch = (int(workgroups), int(waves_per_workgroup))
+
+    def set_attract_launch(self, where: int = DEFAULT_ATTRACT_LAUNCH):
+        """Launch that computes the attractive term: 1 beside phase A, 2 at the
+        end of phase B, 0 automatic (a tuning parameter; the result does not
+        depend on it)."""
+        _ck(lib().hts_set_attract_launch(self.h, int(where)))
+        self.attract_launch = int(where)
 
     def set_item_points(self, s: int):
         """Barnes-Hut work-item size (a tuning parameter)."""

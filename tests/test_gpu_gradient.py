@@ -320,6 +320,40 @@ def test_bh_traversal_launch_shapes_give_the_same_result(ctx, dtype):
         ctx.set_traversal_launch()
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_bh_attract_launch_gives_the_same_result(ctx, dtype):
+    # the attractive rows beside phase A or at the end of phase B: the same
+    # arithmetic per row, so the gradient, Z and counters are the same bit for
+    # bit, with either launch shape of the second kernel
+    X, _, rp, col, val = affinities(3000)
+    Y = embedding(3000, "mid", dtype)
+    val = val.astype(dtype)
+    try:
+        ref = _run_bh(ctx, Y, rp, col, val, 12.0, 0.5, stats=True)
+        for where in (1, 2, 0):
+            for shape in [(0, 1), (7, 4)]:
+                ctx.set_attract_launch(where)
+                ctx.set_traversal_launch(*shape)
+                got = _run_bh(ctx, Y, rp, col, val, 12.0, 0.5, stats=True)
+                assert np.array_equal(got[0], ref[0]) and got[1] == ref[1] and got[2] == ref[2], \
+                    (where, shape)
+        plain = []
+        for where in (1, 2):
+            ctx.set_attract_launch(where)
+            plain.append(_run_bh(ctx, Y, rp, col, val, 12.0, 0.5))
+        assert np.array_equal(plain[0][0], plain[1][0]) and plain[0][1] == plain[1][1]
+    finally:
+        ctx.set_attract_launch()
+        ctx.set_traversal_launch()
+
+
+def test_attract_launch_rejects_other_values(ctx):
+    for where in (-1, 3):
+        with pytest.raises(RuntimeError):
+            ctx.set_attract_launch(where)
+    assert ctx.attract_launch == hts.DEFAULT_ATTRACT_LAUNCH
+
+
 def test_traversal_launch_rejects_bad_shapes(ctx):
     for g_, w_ in [(-1, 4), (16, 3), (16, 8), (0, 0)]:
         with pytest.raises(RuntimeError):

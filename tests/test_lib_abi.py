@@ -74,6 +74,8 @@ def test_item_list_share_needs_a_context():
     assert "ctx is NULL" in hts.last_error()
     assert L.hts_set_traversal_launch(None, 16384, 4) != 0
     assert "ctx is NULL" in hts.last_error()
+    assert L.hts_set_attract_launch(None, 1) != 0
+    assert "ctx is NULL" in hts.last_error()
 
 
 def test_native_driver_input_file(tmp_path):
