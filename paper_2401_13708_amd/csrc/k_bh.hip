@@ -9,8 +9,8 @@
 // distance argument t in double) and adds N_cell w^2 d dd/dy, or joins the
 // set of lanes that need the children.  Leaves are evaluated exactly, skipping
 // the query.  The lanes that need a subtree form a 64-bit mask per depth, kept
-// in two VGPRs used as lane-indexed arrays (readlane and writelane with the
-// depth as the lane), and a mask serves directly as the lane predicate
+// in two VGPRs used as lane-indexed arrays (readlane with the depth to read,
+// a lane select to write), and a mask serves directly as the lane predicate
 // of the masked term.  Node records are read with scalar loads; the next
 // sibling's is in flight while a node is evaluated, and so is the first
 // child's in the walks of the work items (phase A loads it when it descends);
@@ -65,18 +65,6 @@ struct alignas(16) ItemRec {
     uint64_t mask;
     uint64_t pad;
 };
-
-// lane l of (lo, hi) set to the two halves of x (x and l uniform;
-// v_writelane ignores the execution mask).  The lane select goes through m0
-// (one scalar source besides m0 per vector instruction), with a wait state
-// after writing it.
-__device__ __forceinline__ void write_lanes(int &lo, int &hi, uint64_t x, int l) {
-    asm volatile("s_mov_b32 m0, %4\n\ts_nop 0\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
-                 : "+v"(lo), "+v"(hi)
-                 : "s"(uniform((int)(uint32_t)x)), "s"(uniform((int)(uint32_t)(x >> 32))),
-                   "s"(uniform(l))
-                 : "m0");
-}
 
 struct Counters {
     unsigned long long test = 0, acc = 0, pair = 0, step = 0, work = 0, cover = 0;
@@ -163,7 +151,9 @@ __device__ __forceinline__ void walk(const NodeRec<T> *__restrict__ nodes, int M
                 k = next;
                 nrec = over;
             } else if (rej) {
-                write_lanes(mlo, mhi, rej, depth + 1);
+                const bool here = lane == depth + 1;
+                mlo = here ? (int)(uint32_t)rej : mlo;
+                mhi = here ? (int)(uint32_t)(rej >> 32) : mhi;
                 if (THRU) {
                     mc = rej;
                     mdep = depth + 1;
