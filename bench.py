@@ -68,9 +68,11 @@ KERNEL_SOURCES = {"traverse": ["k_bh.hip", "hts_math.hpp", "hts_impl.hpp"],
                   "tree": ["k_tree.hip", "k_sort.hip", "hts_math.hpp", "hts_impl.hpp"]}
 
 
-def _traffic(kernel, windows):
+def _traffic(kernel, windows, setting):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on these windows and the kernel's sources are unchanged since."""
+    was taken on these windows of the same workload setting (N, theta, the
+    attractive rows' launch, the traversal's tuning) and the kernel's sources
+    are unchanged since."""
     path = os.path.join(PROFILE_DIR, "traffic_%s.json" % kernel)
     if not os.path.exists(path):
         return None
@@ -79,6 +81,8 @@ def _traffic(kernel, windows):
     if rec.get("source_hash") != _src_hash(KERNEL_SOURCES[kernel]):
         return None
     if rec.get("windows") != windows:
+        return None
+    if rec.get("setting") != setting:
         return None
     return rec.get("bytes_per_launch")
 
@@ -663,8 +667,14 @@ def bench_single(args):
         del a, b
 
     # roofline of the dominant kernel of the timed windows
+    rows_in_items = hts.attract_in_items(ctx.attract_launch, n)
+    # what a committed traffic record must have been taken with
+    setting = {"n": n, "theta": args.theta, "hsne_lambda": hs, "split_rule": args.split_rule,
+               "item_points": ctx.item_points, "item_list": ctx.item_list,
+               "traversal_launch": list(ctx.traversal_launch), "attract_rows_in_items": rows_in_items}
     names = {"tree": "tree build", "attract": "k_attract",
-             "traverse": "k_bh_top", "items": "k_bh_items (with the attractive rows)",
+             "traverse": "k_bh_top" if rows_in_items else "k_bh_top (with the attractive rows)",
+             "items": "k_bh_items (with the attractive rows)" if rows_in_items else "k_bh_items",
              "finalize": "k_bh_gather + k_bh_finalize", "step": "k_step"}
     kms = {c: v[0] for c, v in kt_tot.items()}
     launches = {c: v[1] for c, v in kt_tot.items()}
@@ -681,19 +691,19 @@ def bench_single(args):
             if hs is None:
                 sh = part(st_tot[:2 * K])
                 flops = sh[0] * F_TEST + (sh[1] + sh[2]) * F_PAIR
-                if dom == "items":
+                if (dom == "items") == rows_in_items:
                     flops += iters * nnz * F_ATTR
             else:  # two launches per iteration: the Euclidean walk, then the hyperbolic one
                 se, sh = part(st_tot[:2 * K]), part(st_tot[2 * K:4 * K])
                 flops = (se[0] * F_TEST_E + (se[1] + se[2]) * F_PAIR_E + sh[0] * F_TEST
                          + (sh[1] + sh[2]) * F_PAIR)
-                if dom == "items":
+                if (dom == "items") == rows_in_items:
                     flops += iters * nnz * (F_ATTR_E + F_ATTR)
             flops /= launches[dom]
             ach = flops / avg_s / 1e12
             roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS, 4),
-                    "traffic": _traffic(dom, windows), "kernel": names[dom],
+                    "traffic": _traffic(dom, windows, setting), "kernel": names[dom],
                     "avg_launch_us": round(avg_s * 1e6, 2), "flops_per_launch": round(flops),
                     "launches": launches[dom], "windows": windows}
         elif dom not in ("traverse", "items"):
@@ -703,7 +713,7 @@ def bench_single(args):
             ach = byts / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": _traffic(dom, windows) if dom in KERNEL_SOURCES else None,
+                    "traffic": _traffic(dom, windows, setting) if dom in KERNEL_SOURCES else None,
                     "kernel": names[dom], "avg_launch_us": round(avg_s * 1e6, 2),
                     "launches": launches[dom], "windows": windows}
 

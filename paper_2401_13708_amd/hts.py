@@ -138,6 +138,13 @@ DEFAULT_ITEM_LIST = 256    # the library's default item-list entries per phase-A
 DEFAULT_ITEMS_GRID = 0     # the library's default phase-B workgroups (0: automatic) ...
 DEFAULT_ITEMS_WAVES = 1    # ... of this many waves
 DEFAULT_ATTRACT_LAUNCH = 0  # the attractive rows' launch: 0 automatic, 1 phase A, 2 phase B
+ATTRACT_WITH_TOP_AT = 131072  # automatic: beside phase A from this many points in the largest job
+
+
+def attract_in_items(where: int, largest_job: int) -> bool:
+    """Whether the Barnes-Hut gradient computes the attractive rows in the
+    traversal's second launch (the library's rule for hts_set_attract_launch)."""
+    return where == 2 or (where == 0 and largest_job < ATTRACT_WITH_TOP_AT)
 
 
 class Context:

@@ -24,3 +24,14 @@ def test_margin_zero_takes_the_fastest():
 def test_default_untimed_or_nothing_timed(times):
     # nothing timed: the default; a default that was not timed cannot be kept
     assert pick_setting(times, 256, 0.02) == (256 if not times else 512)
+
+
+def test_attract_launch_rule_mirrors_the_library():
+    # the library's threshold (k_bh.hip, kAttractWithTopAt) and the binding's
+    import re
+    from pathlib import Path
+    from paper_2401_13708_amd import hts
+    src = (Path(__file__).resolve().parents[1] / "paper_2401_13708_amd" / "csrc" / "k_bh.hip").read_text()
+    assert int(re.search(r"kAttractWithTopAt = (\d+);", src).group(1)) == hts.ATTRACT_WITH_TOP_AT
+    assert hts.attract_in_items(0, 70000) and not hts.attract_in_items(0, 200000)
+    assert hts.attract_in_items(2, 10 ** 6) and not hts.attract_in_items(1, 1000)
