@@ -393,8 +393,8 @@ def iteration_bh(ctx: Context, Y, update, gains, row_ptr, col_idx, p_val, tree: 
                  theta: float, exaggeration: float, eta: float, momentum: float, grad=None, z=None,
                  min_gain: float = 0.01, boundary_eps: float = 1e-5, metric_power: int = 2,
                  stream=None):
-    """Tree, Barnes-Hut gradient and step in one call (the attractive term
-    overlaps the tree build on a second stream); returns grad, z."""
+    """Tree, Barnes-Hut gradient and step in one call, bit for bit the three
+    calls; returns grad, z."""
     for t, nm in ((Y, "Y"), (update, "update"), (gains, "gains")):
         _dev(t, nm, Y.dtype)
     _csr_args(Y, row_ptr, col_idx, p_val)
