@@ -607,8 +607,20 @@ static hts_status iteration_impl(hts_ctx c, hipStream_t st, T *Y, T *U, T *G, in
                                  hts_tree t, double theta, T *grad, double *z_dev, double eta,
                                  double momentum, double min_gain, double boundary_eps,
                                  int32_t metric_power) {
-    HTS_OKR(tree_build<T>(c, st, Y, n, t));
-    HTS_OKR(bh_impl<T>(c, st, Y, n, rp, col, val, ex, nullptr, t, theta, grad, z_dev, nullptr));
+    // the gradient's workspaces first, so that the tree build can do the work
+    // of the gradient's preparation launch (point records, thresholds, the
+    // item-list counter), which is then left out
+    HTS_OKR(tree_single_job(st, t, n));
+    HTS_OKR(ensure(c->pts, (size_t)n * sizeof(PointRec<T>)));
+    HTS_OKR(ensure(c->fattr, (size_t)n * 2 * sizeof(T)));
+    unsigned *counter = nullptr;
+    HTS_OKR(bh_item_counter<T>(c, t, n, &counter));
+    PointRec<T> *pts = (PointRec<T> *)c->pts.p;
+    const TreeExtras<T> extras{pts, theta, counter};
+    HTS_OKR(tree_build<T>(c, st, Y, n, t, &extras));
+    HTS_OKR((launch_bh_repulsion<T, 0>(c, st, t, n, BhPrep<T>{Y, theta, false, false, false}, pts, rp,
+                                       col, val, (T *)c->fattr.p, ex, nullptr, false, 1.0, grad,
+                                       z_dev, nullptr)));
     return launch_step<T>(c, st, Y, U, G, grad, n, eta, momentum, nullptr, nullptr, nullptr,
                           min_gain, boundary_eps, metric_power);
 }

@@ -190,8 +190,20 @@ struct TimedScope {
 template <typename T>
 hts_status launch_prep_points(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, PointRec<T> *pts);
 
+// What a tree build can also do for the Barnes-Hut gradient that follows it
+// (the work of the gradient's preparation launch, which is then left out):
+// the point records of Y in input order (pts), the criterion thresholds of
+// the internal nodes for theta, and the clearing of the item-list counter.
 template <typename T>
-hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tree t);
+struct TreeExtras {
+    PointRec<T> *pts;
+    double theta;
+    unsigned *dense_count;
+};
+
+template <typename T>
+hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tree t,
+                      const TreeExtras<T> *extras = nullptr);
 
 // device tables of a one-job layout over n points (when n changed)
 hts_status tree_single_job(hipStream_t st, hts_tree t, int64_t n);
@@ -218,15 +230,23 @@ hts_status launch_attract(hts_ctx ctx, hipStream_t st, const PointRec<T> *pts, c
                           bool timed = true);
 
 // What the launch that starts a traversal also does: the point records of Y
-// into pts (points) and the criterion thresholds of the tree's hyperbolic
-// nodes for theta (thresholds).
+// into pts (points), the criterion thresholds of the tree's hyperbolic nodes
+// for theta (thresholds) and the clearing of the item-list counter (clear;
+// when none of the three is asked, the launch is left out).
 template <typename T>
 struct BhPrep {
     const T *Y;
     double theta;
     bool points;
     bool thresholds;
+    bool clear = true;
 };
+
+// The item-list counter of a one-job traversal of n points on ctx (the
+// workspace is allocated as the traversal will use it), for a tree build
+// that clears it (TreeExtras).
+template <typename T>
+hts_status bh_item_counter(hts_ctx ctx, hts_tree t, int64_t n, unsigned **counter);
 
 // Barnes-Hut repulsion over the tree and the combine g = 4 (a F_attr - F_rep / Z)
 // ex_job: per-job exaggeration (device, [J]) or NULL for ex; z_dev receives

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_bh_prepare(const T *__restrict__ Y, 
                                                        unsigned *__restrict__ dense_count,
                                                        uint32_t *__restrict__ err) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i == 0) *dense_count = 0u;
+    if (i == 0 && dense_count) *dense_count = 0u;
     if (points && i < n) prep_point<T>(Y, i, pts, err);
     if (thresholds) {
         const int64_t M = *d_m;
@@ -623,6 +623,46 @@ __global__ __launch_bounds__(kBlock) void k_bh_finalize(
     grad[2 * (int64_t)i + 1] = oy;
 }
 
+// The traversal's workspace (item list, partials, per-block sums) in ctx->part:
+// the offsets of its 11 regions and the total, for nqb query blocks and n
+// points (with the counters' region when stats are asked).
+struct BhLayout {
+    static constexpr int R = 11;
+    size_t off[R];
+    size_t tot;
+};
+template <typename T>
+static BhLayout bh_layout(hts_ctx ctx, int64_t nqb, int64_t n, bool stats) {
+    const int64_t nw = nqb * kTopSlots;
+    const int share = ctx->list_items < kItemCap ? ctx->list_items : kItemCap;
+    const int64_t slots = nw * share;
+    const size_t b_base = (size_t)nw * 4, b_nit = (size_t)nw * 4;
+    const size_t b_part0 = (size_t)kTopSlots * n * 2 * sizeof(T), b_ztop = (size_t)nw * 8;
+    const size_t b_part = (size_t)slots * kWave * 2 * sizeof(T), b_zitem = (size_t)slots * 8;
+    const size_t b_frep = (size_t)n * 2 * sizeof(T), b_zq = (size_t)nqb * 8;
+    const size_t b_st = stats ? (size_t)(slots + nw) * kStats * 4 : 0;
+    const size_t b_cnt = 256, b_dense = (size_t)slots * sizeof(ItemRec);
+    const size_t sizes[BhLayout::R] = {b_base, b_nit, b_part0, b_ztop, b_part, b_zitem,
+                                       b_frep, b_zq, b_st, b_cnt, b_dense};
+    BhLayout L;
+    L.tot = 0;
+    for (int a = 0; a < BhLayout::R; ++a) {
+        L.off[a] = L.tot;
+        L.tot += (sizes[a] + 255) & ~(size_t)255;
+    }
+    return L;
+}
+
+template <typename T>
+hts_status bh_item_counter(hts_ctx ctx, hts_tree t, int64_t n, unsigned **counter) {
+    const BhLayout L = bh_layout<T>(ctx, t->nqb, n, false);
+    HTS_OKR(ensure(ctx->part, L.tot));
+    *counter = (unsigned *)((char *)ctx->part.p + L.off[9]);
+    return HTS_OK;
+}
+template hts_status bh_item_counter<float>(hts_ctx, hts_tree, int64_t, unsigned **);
+template hts_status bh_item_counter<double>(hts_ctx, hts_tree, int64_t, unsigned **);
+
 template <typename T, int MET>
 hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t n,
                                BhPrep<T> prep, PointRec<T> *pts, const int64_t *rp,
@@ -636,21 +676,9 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     const int64_t slots = nw * share;
     const int S = ctx->item_points;
     // workspace: item list, partials, per-block sums
-    const size_t b_base = (size_t)nw * 4, b_nit = (size_t)nw * 4;
-    const size_t b_part0 = (size_t)kTopSlots * n * 2 * sizeof(T), b_ztop = (size_t)nw * 8;
-    const size_t b_part = (size_t)slots * kWave * 2 * sizeof(T), b_zitem = (size_t)slots * 8;
-    const size_t b_frep = (size_t)n * 2 * sizeof(T), b_zq = (size_t)nqb * 8;
-    const size_t b_st = stats ? (size_t)(slots + nw) * kStats * 4 : 0;
-    const size_t b_cnt = 256, b_dense = (size_t)slots * sizeof(ItemRec);
-    constexpr int R = 11;
-    size_t off[R], tot = 0;
-    const size_t sizes[R] = {b_base, b_nit, b_part0, b_ztop, b_part, b_zitem,
-                             b_frep, b_zq, b_st, b_cnt, b_dense};
-    for (int a = 0; a < R; ++a) {
-        off[a] = tot;
-        tot += (sizes[a] + 255) & ~(size_t)255;
-    }
-    HTS_OKR(ensure(ctx->part, tot));
+    const BhLayout L = bh_layout<T>(ctx, nqb, n, stats != nullptr);
+    const size_t *off = L.off;
+    HTS_OKR(ensure(ctx->part, L.tot));
     char *base = (char *)ctx->part.p;
     int *item_base = (int *)(base + off[0]);
     int *nitems = (int *)(base + off[1]);
@@ -681,9 +709,10 @@ hts_status launch_bh_repulsion(hts_ctx ctx, hipStream_t st, hts_tree t, int64_t 
     if (gi < 1) gi = 1;          // an empty list (no items can be handed over)
     // one thread per point, and the node thresholds strided over the same grid
     const int64_t gp = cdiv(n, kBlock) > 64 ? cdiv(n, kBlock) : 64;
-    hipLaunchKernelGGL(k_bh_prepare<T>, dim3(gp), dim3(kBlock), 0, st, prep.Y, n, pts, prep.points,
-                       (NodeRec<T> *)t->nodes, t->r_cell, t->d_m, prep.theta, prep.thresholds,
-                       dense_count, ctx->d_err);
+    if (prep.points || prep.thresholds || prep.clear)
+        hipLaunchKernelGGL(k_bh_prepare<T>, dim3(gp), dim3(kBlock), 0, st, prep.Y, n, pts,
+                           prep.points, (NodeRec<T> *)t->nodes, t->r_cell, t->d_m, prep.theta,
+                           prep.thresholds, prep.clear ? dense_count : nullptr, ctx->d_err);
     {
         TimedScope ts(ctx, st, HTS_K_TRAVERSE);
         const int64_t top_blocks = cdiv(nw, kBlock / kWave);

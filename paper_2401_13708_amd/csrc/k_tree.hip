@@ -267,7 +267,9 @@ __global__ __launch_bounds__(kBlock) void k_sorted(const T *__restrict__ Y, int6
                                                    int32_t *__restrict__ cnt,
                                                    DD3 *__restrict__ q,
                                                    int32_t *__restrict__ cnt_part,
-                                                   DD3 *__restrict__ q_part) {
+                                                   DD3 *__restrict__ q_part,
+                                                   PointRec<T> *__restrict__ pts_in,
+                                                   uint32_t *__restrict__ err) {
     __shared__ int scnt[kBlock];
     __shared__ DD3 sq[kBlock];
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -275,6 +277,9 @@ __global__ __launch_bounds__(kBlock) void k_sorted(const T *__restrict__ Y, int6
     DD3 v = dd_zero();
     if (i < n) {
         uint32_t p = perm[i];
+        // for a gradient that follows: the input-order record of this point,
+        // as its preparation launch writes it
+        if (pts_in) prep_point<T>(Y, p, pts_in, err);
         T x = Y[2 * p], y = Y[2 * p + 1];
         double xd = (double)x, yd = (double)y;
         double r2 = xd * xd + yd * yd;
@@ -536,10 +541,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
                                                  NodeRec<T> *__restrict__ nodes,
                                                  double *__restrict__ r_cell,
                                                  const int32_t *__restrict__ node_first,
-                                                 const int32_t *__restrict__ d_m, int split) {
+                                                 const int32_t *__restrict__ d_m, int split,
+                                                 double theta, unsigned *__restrict__ dense_count) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int32_t M = *d_m;
     if (k >= M) return;
+    if (k == 0 && dense_count) *dense_count = 0u;  // for a traversal that follows
     const int64_t i = node_first[k];
     const NodeSpan sp = node_span(keys, i, n, L);
     const int l = sp.s + (int)(k - node_start[i]);
@@ -568,8 +575,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
         rec.my = my;
         rec.ib = 1.0 / (1.0 - ((double)mx * (double)mx + (double)my * (double)my));
     }
-    rec.c = leaf ? __longlong_as_double((long long)i) : 0.0;
-    nodes[k] = rec;
     double lo, hi;
     cell_radii(key, l, L, root, split, lo, hi);
     // hyperbolic diameter: the larger of the outer-arc chord and the
@@ -581,7 +586,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint64_t *__restrict__ ke
     const double dr = hi - lo;
     const double t_diag = 2.0 * (dr * dr + 4.0 * lo * hi * s * s) / (alo * ahi);
     const double t = fmax(t_outer, t_diag);
-    r_cell[k] = log1p(t + sqrt(t * (t + 2.0)));
+    const double rc = log1p(t + sqrt(t * (t + 2.0)));
+    r_cell[k] = rc;
+    // a leaf keeps its first point; an internal node gets its criterion
+    // threshold when a gradient that follows gave theta (theta < 0: later)
+    rec.c = leaf ? __longlong_as_double((long long)i) : theta >= 0.0 ? node_threshold(rc, theta) : 0.0;
+    nodes[k] = rec;
 }
 
 __global__ void k_single_job(int64_t *__restrict__ job_off, int32_t *__restrict__ job_qb,
@@ -608,7 +618,8 @@ hts_status tree_single_job(hipStream_t st, hts_tree t, int64_t n) {
 constexpr int64_t kOwnScanBlocks = 1024;
 
 template <typename T>
-hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tree t) {
+hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tree t,
+                      const TreeExtras<T> *extras) {
     TimedScope ts(ctx, st, HTS_K_TREE);
     HTS_OKR(tree_single_job(st, t, n));
     const int L = t->max_depth;
@@ -622,7 +633,8 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     HTS_OKR(radix_sort_pairs(st, t->keys_in, t->idx_in, t->keys, t->perm, n, 2 * L + t->job_bits,
                              t->sort_tmp));
     hipLaunchKernelGGL(k_sorted<T>, dim3(nb), dim3(kBlock), 0, st, Y, n, t->keys, t->perm, L,
-                       (PointRec<T> *)t->spts, t->node_start, t->psum, t->ncnt_part, t->q_part);
+                       (PointRec<T> *)t->spts, t->node_start, t->psum, t->ncnt_part, t->q_part,
+                       extras ? extras->pts : nullptr, ctx->d_err);
     HTS_HIP(hipGetLastError());
     if (nb <= kOwnScanBlocks) {
         hipLaunchKernelGGL(k_scan_apply<true>, dim3(nb), dim3(kBlock), 0, st, t->node_start, t->psum,
@@ -642,7 +654,8 @@ hts_status tree_build(hts_ctx ctx, hipStream_t st, const T *Y, int64_t n, hts_tr
     if (nbm > cdiv(t->cap_nodes, kBlock)) nbm = cdiv(t->cap_nodes, kBlock);
     hipLaunchKernelGGL(k_emit<T>, dim3(nbm), dim3(kBlock), 0, st, t->keys, n, L,
                        (const PointRec<T> *)t->spts, t->node_start, t->psum, t->root, t->sinhalf,
-                       (NodeRec<T> *)t->nodes, t->r_cell, t->node_first, t->d_m, t->split_rule);
+                       (NodeRec<T> *)t->nodes, t->r_cell, t->node_first, t->d_m, t->split_rule,
+                       extras ? extras->theta : -1.0, extras ? extras->dense_count : nullptr);
     HTS_HIP(hipGetLastError());
     t->n = n;
     t->dtype = sizeof(T) == 8 ? HTS_F64 : HTS_F32;
@@ -828,7 +841,9 @@ hts_status tree_euclid(hts_ctx ctx, hipStream_t st, hts_tree t, double theta) {
 template hts_status tree_euclid<float>(hts_ctx, hipStream_t, hts_tree, double);
 template hts_status tree_euclid<double>(hts_ctx, hipStream_t, hts_tree, double);
 
-template hts_status tree_build<float>(hts_ctx, hipStream_t, const float *, int64_t, hts_tree);
-template hts_status tree_build<double>(hts_ctx, hipStream_t, const double *, int64_t, hts_tree);
+template hts_status tree_build<float>(hts_ctx, hipStream_t, const float *, int64_t, hts_tree,
+                                     const TreeExtras<float> *);
+template hts_status tree_build<double>(hts_ctx, hipStream_t, const double *, int64_t, hts_tree,
+                                      const TreeExtras<double> *);
 
 }  // namespace hts
