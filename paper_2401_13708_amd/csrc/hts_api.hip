@@ -57,14 +57,14 @@ TimedScope::TimedScope(hts_ctx c, hipStream_t s, int k) : ctx(c), st(s), cls(k) 
         }
     }
     b = tm.pool[tm.used++];
-    hipEventRecord(b, st);
+    (void)hipEventRecord(b, st);
 }
 
 TimedScope::~TimedScope() {
     if (!b) return;
     Timing &tm = ctx->timing;
     hipEvent_t e = tm.pool[tm.used++];
-    hipEventRecord(e, st);
+    (void)hipEventRecord(e, st);
     tm.recs.push_back({cls, b, e});
 }
 
@@ -102,7 +102,7 @@ hts_status hts_create(int32_t device, hts_ctx *out) {
     e = hipMemset(c->d_err, 0, 64);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        hipFree(c->d_err);
+        (void)hipFree(c->d_err);
         delete c;
         return hip_fail(e, "hipMemset(error word)");
     }
@@ -112,15 +112,15 @@ hts_status hts_create(int32_t device, hts_ctx *out) {
 
 hts_status hts_destroy(hts_ctx c) {
     if (!c) return fail(HTS_EINVAL, "hts_destroy: ctx is NULL");
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
     Buffer *bufs[] = {&c->pts, &c->fattr, &c->frep, &c->zpart, &c->part, &c->spare};
     for (Buffer *b : bufs)
-        if (b->p) hipFree(b->p);
+        if (b->p) (void)hipFree(b->p);
     for (Buffer &b : c->aff)
-        if (b.p) hipFree(b.p);
-    for (hipEvent_t e : c->timing.pool) hipEventDestroy(e);
-    hipFree(c->d_err);
+        if (b.p) (void)hipFree(b.p);
+    for (hipEvent_t e : c->timing.pool) (void)hipEventDestroy(e);
+    (void)hipFree(c->d_err);
     delete c;
     return HTS_OK;
 }
@@ -243,14 +243,14 @@ hts_status hts_tree_create(hts_ctx c, int64_t n_max, int32_t max_depth, hts_tree
 
 hts_status hts_tree_destroy(hts_tree t) {
     if (!t) return fail(HTS_EINVAL, "hts_tree_destroy: tree is NULL");
-    hipSetDevice(t->device);  // not through ctx, which may be destroyed already
-    hipDeviceSynchronize();
+    (void)hipSetDevice(t->device);  // not through ctx, which may be destroyed already
+    (void)hipDeviceSynchronize();
     void *ptrs[] = {t->job_off, t->job_qb, t->qb_job, t->pjob, t->root, t->r, t->mm,
                     t->keys_in, t->keys, t->idx_in, t->perm, t->sort_tmp, t->ncnt_part,
                     t->q_part, t->node_start, t->psum, t->d_m, t->spts, t->nodes, t->r_cell,
                     t->node_first, t->sinhalf, t->enodes, t->epsum, t->epart};
     for (void *p : ptrs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     delete t;
     return HTS_OK;
 }
@@ -530,7 +530,7 @@ static hts_status tree_euclid_alloc(hts_tree t) {
         if (e != hipSuccess) {
             for (auto &b : allocs)
                 if (*b.p) {
-                    hipFree(*b.p);
+                    (void)hipFree(*b.p);
                     *b.p = nullptr;
                 }
             return hip_fail(e, "hipMalloc(euclidean nodes)");
