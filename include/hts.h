@@ -309,7 +309,7 @@ hts_status hts_jobs_schedule(hts_ctx ctx, hts_stream stream, int32_t n_jobs,
 /* Traversal work split (a tuning parameter, not part of the method): the
  * Barnes-Hut walk hands every rejected cell of at most item_points points to
  * a separate short walk.  Results differ between settings only by the order
- * of floating-point sums.  Default 256; applies to later calls on ctx. */
+ * of floating-point sums.  Default 288; applies to later calls on ctx. */
 hts_status hts_set_item_points(hts_ctx ctx, int32_t item_points);
 
 /* Size of the list that carries those short walks between the two kernels of

@@ -176,7 +176,7 @@ TRAVERSAL_LAUNCHES = ((0, 1), (16384, 4), (65536, 2), (32768, 1), (65536, 1), (1
                       (262144, 1))
 
 
-def autotune_traversal(ctx: hts.Context, jobs: list[Job], candidates=(128, 256, 512, 1024, 2048),
+def autotune_traversal(ctx: hts.Context, jobs: list[Job], candidates=(128, 256, 288, 512, 1024, 2048),
                        launches=TRAVERSAL_LAUNCHES, warm: int = 100, reps: int = 8,
                        theta: float = 0.5, margin: float = 0.02
                        ) -> tuple[tuple[int, tuple[int, int], int], dict]:
@@ -216,7 +216,7 @@ def autotune_traversal(ctx: hts.Context, jobs: list[Job], candidates=(128, 256, 
 
     times = {}
     by_s = {}
-    for S in candidates:
+    for S in sorted(set(candidates) | {hts.DEFAULT_ITEM_POINTS}):  # the default is always timed
         ctx.set_item_points(S)
         by_s[S] = times["S=%d" % S] = timed()
     best_s = pick_setting(by_s, hts.DEFAULT_ITEM_POINTS, margin)

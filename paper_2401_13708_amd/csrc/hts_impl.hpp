@@ -94,7 +94,7 @@ struct Buffer {
 
 struct hts_ctx_s {
     int device = 0;
-    int32_t item_points = 256;  // Barnes-Hut work-item size S (hts_set_item_points)
+    int32_t item_points = 288;  // Barnes-Hut work-item size S (hts_set_item_points)
     int32_t list_items = 256;   // item-list entries per phase-A wave (hts_set_item_list)
     int32_t items_grid = 0;     // phase-B workgroups at most, 0: automatic (hts_set_traversal_launch)
     int32_t items_waves = 1;    // waves per phase-B workgroup

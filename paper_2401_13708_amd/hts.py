@@ -133,7 +133,7 @@ def _dev(t: torch.Tensor, name: str, dtype=None):
 # points covered), then the same six for its second kernel
 STATS_BLOCK = 6
 STATS_PER_CALL = 2 * STATS_BLOCK
-DEFAULT_ITEM_POINTS = 256  # the library's default work-item size
+DEFAULT_ITEM_POINTS = 288  # the library's default work-item size
 DEFAULT_ITEM_LIST = 256    # the library's default item-list entries per phase-A wave
 DEFAULT_ITEMS_GRID = 0     # the library's default phase-B workgroups (0: automatic) ...
 DEFAULT_ITEMS_WAVES = 1    # ... of this many waves
